@@ -1,0 +1,236 @@
+"""Seeded synthetic workloads for the wildfire stepper.
+
+This module only *generates inputs*: fuel rasters, ignition points, wind
+descriptions and the initial spline-coefficient arrays of temperature and fuel.
+It holds none of the stepper's arithmetic (no quadrature, no matrices, no
+solves), so both the HIP library and the CPU oracle can start from the same
+arrays.
+
+The paper's own workloads (satellite-derived fuel maps of the Valparaiso and
+Gran Canaria fires, Section 6) are not available; these generators stand in for
+them with fields shaped like regional domains: a fuel raster in [0, 1] with
+burnable patches and straight zero-fuel firebreaks, Gaussian-smoothed
+ignitions added to the ambient temperature (Section 2.1, "Ignition
+initialization"), and a steady wind.
+
+Initial coefficients.  The state is a pair of coefficient arrays on the
+tensor-product B-spline space (uniform open knots, degree p).  A field given as
+a function (the ignition Gaussians) or as a per-element raster (fuel) is turned
+into coefficients by sampling it at the Greville abscissae -- the
+variation-diminishing spline approximation -- so coefficients, and therefore
+the spline values, stay within the range of the input.  Layout: dof (i, j) at
+``[i, j]`` of an ``(nel_x + p, nel_y + p)`` float64 array.
+"""
+from __future__ import annotations
+
+import dataclasses
+from typing import List, Optional, Tuple
+
+import numpy as np
+
+T_AMBIENT = 300.0
+
+
+@dataclasses.dataclass
+class Wind:
+    """b(x, y).  'const': (bx, by).  'sincos': (bx + ax sin 2 pi y^, by + ay cos 2 pi x^)
+    with x^, y^ the coordinates scaled to [0, 1].  (bbar_x, bbar_y) is the
+    constant part that the scheme treats implicitly (the domain mean of b)."""
+    kind: str = "const"
+    bx: float = 0.0
+    by: float = 0.0
+    ax: float = 0.0
+    ay: float = 0.0
+    bbar_x: Optional[float] = None
+    bbar_y: Optional[float] = None
+
+    def as_dict(self) -> dict:
+        d = dataclasses.asdict(self)
+        if d["bbar_x"] is None:
+            d["bbar_x"] = self.bx
+        if d["bbar_y"] is None:
+            d["bbar_y"] = self.by
+        return d
+
+
+@dataclasses.dataclass
+class Scenario:
+    name: str
+    nel_x: int
+    nel_y: int
+    p: int
+    len_x: float
+    len_y: float
+    dt: float
+    scheme: str          # 'pr' or 'strang'
+    steps: int
+    wind: Wind
+    seed: int
+    ignitions: List[Tuple[float, float]]
+    T0: Optional[np.ndarray] = None
+    fuel0: Optional[np.ndarray] = None
+    fuel_raster: Optional[np.ndarray] = None
+
+    @property
+    def Nx(self) -> int:
+        return self.nel_x + self.p
+
+    @property
+    def Ny(self) -> int:
+        return self.nel_y + self.p
+
+    @property
+    def ndof(self) -> int:
+        return self.Nx * self.Ny
+
+    def wind_dict(self) -> dict:
+        return self.wind.as_dict()
+
+
+# ---------------------------------------------------------------------------
+# sampling points
+# ---------------------------------------------------------------------------
+def greville(nel: int, p: int) -> np.ndarray:
+    """Greville abscissae in [0, 1] of the uniform open knot vector with nel
+    elements: xi_i = (t_{i+1} + ... + t_{i+p}) / p, i = 0 .. nel+p-1."""
+    k = np.arange(nel + 2 * p + 1)
+    t = np.clip((k - p) / nel, 0.0, 1.0)
+    return np.array([t[i + 1:i + p + 1].mean() for i in range(nel + p)])
+
+
+def _element_of(xi: np.ndarray, nel: int) -> np.ndarray:
+    return np.minimum((xi * nel).astype(np.int64), nel - 1)
+
+
+def raster_to_coeffs(raster: np.ndarray, p: int) -> np.ndarray:
+    """Per-element raster (nel_x, nel_y) -> coefficients: the raster value of
+    the element holding each Greville point."""
+    nx, ny = raster.shape
+    ex = _element_of(greville(nx, p), nx)
+    ey = _element_of(greville(ny, p), ny)
+    return np.ascontiguousarray(raster[np.ix_(ex, ey)], dtype=np.float64)
+
+
+def ignition_coeffs(nel_x: int, nel_y: int, p: int, centres, sigma: float = 0.05,
+                    peak: float = 600.0, ambient: float = T_AMBIENT) -> np.ndarray:
+    """ambient + peak * max_k exp(-|x^ - c_k|^2 / (2 sigma^2)) at the Greville points."""
+    gx = greville(nel_x, p)[:, None]
+    gy = greville(nel_y, p)[None, :]
+    bump = np.zeros((gx.size, gy.size))
+    for cx, cy in centres:
+        bump = np.maximum(bump, np.exp(-((gx - cx) ** 2 + (gy - cy) ** 2) / (2.0 * sigma ** 2)))
+    return np.ascontiguousarray(ambient + peak * bump, dtype=np.float64)
+
+
+# ---------------------------------------------------------------------------
+# fuel rasters
+# ---------------------------------------------------------------------------
+def fuel_iid(rng: np.random.Generator, nel_x: int, nel_y: int, lo=0.5, hi=1.0) -> np.ndarray:
+    return rng.uniform(lo, hi, size=(nel_x, nel_y))
+
+
+def fuel_filtered(rng: np.random.Generator, nel_x: int, nel_y: int, sigma_cells=8.0,
+                  mean=0.6, spread=0.25, n_breaks=3, break_width=4) -> np.ndarray:
+    """White noise -> Gaussian filter (sigma in cells, reflecting borders,
+    truncated at 4 sigma) -> standardised -> clip(mean + spread z, 0, 1), then
+    `n_breaks` straight zero-fuel strips `break_width` cells wide, each
+    horizontal or vertical with probability 1/2, offset uniform in
+    [0.1, 0.9) of the extent, running the full length of the domain."""
+    from scipy.ndimage import gaussian_filter
+
+    z = rng.standard_normal((nel_x, nel_y))
+    z = gaussian_filter(z, sigma=sigma_cells, mode="reflect", truncate=4.0)
+    z = (z - z.mean()) / max(z.std(), 1e-300)
+    fuel = np.clip(mean + spread * z, 0.0, 1.0)
+    for _ in range(n_breaks):
+        vertical = rng.uniform() < 0.5
+        extent = nel_x if vertical else nel_y
+        off = int(rng.uniform(0.1, 0.9) * extent)
+        sl = slice(off, min(off + break_width, extent))
+        if vertical:
+            fuel[sl, :] = 0.0
+        else:
+            fuel[:, sl] = 0.0
+    return fuel
+
+
+# ---------------------------------------------------------------------------
+# the workloads
+# ---------------------------------------------------------------------------
+def _finish(sc: Scenario, raster: np.ndarray) -> Scenario:
+    sc.fuel_raster = raster
+    sc.fuel0 = raster_to_coeffs(raster, sc.p)
+    sc.T0 = ignition_coeffs(sc.nel_x, sc.nel_y, sc.p, sc.ignitions)
+    return sc
+
+
+def plain_pr_64(seed: int = 0, nel: int = 64, steps: int = 20) -> Scenario:
+    """64x64 quadratic, Peaceman-Rachford, dt 1e-3, 20 steps; one ignition with
+    centre uniform in [0.3, 0.7]^2; fuel i.i.d. U[0.5, 1] per element; constant
+    wind (1.0, 0.5)."""
+    rng = np.random.default_rng(seed)
+    centre = tuple(rng.uniform(0.3, 0.7, size=2))
+    raster = fuel_iid(rng, nel, nel)
+    sc = Scenario(name=f"plain_pr_{nel}", nel_x=nel, nel_y=nel, p=2, len_x=float(nel),
+                  len_y=float(nel), dt=1e-3, scheme="pr", steps=steps,
+                  wind=Wind("const", 1.0, 0.5), seed=seed, ignitions=[centre])
+    return _finish(sc, raster)
+
+
+def regional_strang(seed: int = 1, nel: int = 1024, steps: int = 200, p: int = 2,
+                    dt: float = 5e-4) -> Scenario:
+    """nel^2 quadratic, Strang with Crank-Nicolson substeps, dt 5e-4; filtered
+    fuel map with 3 firebreaks; wind (1 + 0.3 sin 2 pi y^, 0.5 cos 2 pi x^)
+    (mean (1, 0)); 3 ignitions with centres uniform in [0.1, 0.9]^2."""
+    rng = np.random.default_rng(seed)
+    raster = fuel_filtered(rng, nel, nel)
+    centres = [tuple(rng.uniform(0.1, 0.9, size=2)) for _ in range(3)]
+    sc = Scenario(name=f"regional_strang_{nel}", nel_x=nel, nel_y=nel, p=p,
+                  len_x=float(nel), len_y=float(nel), dt=dt, scheme="strang", steps=steps,
+                  wind=Wind("sincos", bx=1.0, by=0.0, ax=0.3, ay=0.5, bbar_x=1.0, bbar_y=0.0),
+                  seed=seed, ignitions=centres)
+    return _finish(sc, raster)
+
+
+def ensemble_member(seed: int, sizes=(256, 384, 512, 768, 1024), p: int = 2,
+                    scheme: str = "strang", steps: int = 300, dt: float = 5e-4) -> Scenario:
+    """One ensemble scenario: grid drawn from `sizes`, its own filtered fuel
+    map, constant wind of magnitude U[0, 3] and direction U[0, 2 pi), and 1-4
+    ignitions."""
+    rng = np.random.default_rng(seed)
+    nel = int(rng.choice(np.asarray(sizes)))
+    mag = rng.uniform(0.0, 3.0)
+    ang = rng.uniform(0.0, 2.0 * np.pi)
+    k = int(rng.integers(1, 5))
+    raster = fuel_filtered(rng, nel, nel)
+    centres = [tuple(rng.uniform(0.1, 0.9, size=2)) for _ in range(k)]
+    sc = Scenario(name=f"member_{seed}_{nel}", nel_x=nel, nel_y=nel, p=p, len_x=float(nel),
+                  len_y=float(nel), dt=dt, scheme=scheme, steps=steps,
+                  wind=Wind("const", mag * np.cos(ang), mag * np.sin(ang)), seed=seed,
+                  ignitions=centres)
+    return _finish(sc, raster)
+
+
+def mixed_ensemble(n_members: int = 64, base_seed: int = 1000, **kw) -> List[Scenario]:
+    return [ensemble_member(base_seed + m, **kw) for m in range(n_members)]
+
+
+def cubic_ensemble(n_members: int = 16, base_seed: int = 2000, nel: int = 2048,
+                   scheme: str = "strang", steps: int = 500) -> List[Scenario]:
+    return [ensemble_member(base_seed + m, sizes=(nel,), p=3, scheme=scheme, steps=steps)
+            for m in range(n_members)]
+
+
+def small_case(seed: int, nel_x: int, nel_y: int, p: int, scheme: str, dt: float = 1e-3,
+               wind: Optional[Wind] = None, n_ign: int = 2, filtered: bool = False) -> Scenario:
+    """Small random case for parity tests (several tiles and ragged tails)."""
+    rng = np.random.default_rng(seed)
+    raster = (fuel_filtered(rng, nel_x, nel_y, sigma_cells=2.0) if filtered
+              else fuel_iid(rng, nel_x, nel_y))
+    centres = [tuple(rng.uniform(0.2, 0.8, size=2)) for _ in range(n_ign)]
+    if wind is None:
+        wind = Wind("sincos", bx=0.7, by=-0.2, ax=0.3, ay=0.5, bbar_x=0.7, bbar_y=-0.2)
+    sc = Scenario(name=f"small_{nel_x}x{nel_y}_p{p}_{scheme}", nel_x=nel_x, nel_y=nel_y, p=p,
+                  len_x=float(nel_x), len_y=float(nel_y), dt=dt, scheme=scheme, steps=1,
+                  wind=wind, seed=seed, ignitions=centres)
+    return _finish(sc, raster)
