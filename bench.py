@@ -1,0 +1,191 @@
+#!/usr/bin/env python
+"""Throughput of the quasi-implicit IGA-ADS wildfire stepper on one MI355X.
+
+Workload: 1024 x 1024 quadratic B-spline elements (1026^2 = 1,052,676 dofs),
+Strang splitting with Crank-Nicolson substeps, dt = 5e-4, seeded synthetic
+regional inputs (filtered fuel map with 3 firebreaks, 3 Gaussian ignitions,
+wind (1 + 0.3 sin 2 pi y^, 0.5 cos 2 pi x^)).  The headline value is the
+FP32-with-FP64-refinement stepper in DOF-steps/s; the FP64 stepper on the same
+inputs is reported beside it.
+
+One JSON line on stdout.  `roofline` describes the dominant kernel of the FP32
+step (measured here with HIP events on the stream it runs on);
+`cpu_baseline` is the FP64 CPU oracle timed on the host cores on a bounded
+sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0           # MI355X HBM3E
+FP32_VALU_PEAK = 157.3          # TFLOP/s, MI355X vector FP32 (published)
+FP64_VALU_PEAK = 78.6           # TFLOP/s, MI355X vector FP64
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--nel", type=int, default=1024)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--kernel-reps", type=int, default=50)
+    return ap.parse_args()
+
+
+def time_steps(pl, sc, steps, warmup, torch):
+    """Graph-replayed timed region of exactly `steps` steps after `warmup`
+    eager steps; the graphs are captured beforehand on the same buffers."""
+    dt = pl.dtype
+    T0 = torch.tensor(sc.T0, dtype=dt, device="cuda")
+    F0 = torch.tensor(sc.fuel0, dtype=dt, device="cuda")
+    T, F = T0.clone(), F0.clone()
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        pl.run(T, F, steps, stream)            # captures the graphs (untimed)
+        T.copy_(T0)
+        F.copy_(F0)
+        for _ in range(warmup):
+            pl.step(T, F, stream)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    with torch.cuda.stream(stream):
+        t0 = time.perf_counter()
+        e0.record(stream)
+        pl.run(T, F, steps, stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+    wall = t1 - t0
+    ev = e0.elapsed_time(e1) / 1e3
+    assert torch.isfinite(T).all() and torch.isfinite(F).all()
+    return wall, ev, T, F
+
+
+def kernel_times(pl, sc, reps, torch):
+    """Average duration of each kernel of one step, launched through the C ABI
+    on one stream between HIP events (same grids as inside the step)."""
+    dt = pl.dtype
+    T = torch.tensor(sc.T0, dtype=dt, device="cuda")
+    F = torch.tensor(sc.fuel0, dtype=dt, device="cuda")
+    R, RF = torch.empty_like(T), torch.empty_like(T)
+    X = torch.randn_like(T)
+    stream = torch.cuda.Stream()
+    out = {}
+    cases = {
+        "assemble_s1_fuel": lambda: pl.assemble_rhs(0, T, F, R, RF, stream),
+        "assemble_s3": lambda: pl.assemble_rhs(2, T, F, R, None, stream),
+        "sweep_x_A": lambda: pl.line_solve(0, 0, X, stream),
+        "sweep_y_M": lambda: pl.line_solve(1, 1, X, stream),
+        "sweep_y_cn": lambda: pl.line_solve(1, 2, X, stream),
+    }
+    with torch.cuda.stream(stream):
+        for name, fn in cases.items():
+            for _ in range(3):
+                fn()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(reps):
+                fn()
+            e1.record(stream)
+            torch.cuda.synchronize()
+            out[name] = e0.elapsed_time(e1) / 1e3 / reps
+            if name.startswith("sweep"):
+                X.copy_(torch.randn_like(X))
+    return out
+
+
+def cpu_baseline(sc, budget_s):
+    import oracle
+    d = oracle.desc_from_scenario(sc)
+    threads = oracle.get_threads()
+    T, F = sc.T0, sc.fuel0
+    t0 = time.perf_counter()
+    T, F = oracle.step(d, T, F)
+    one = time.perf_counter() - t0
+    n = max(1, int(budget_s / max(one, 1e-6)) - 1)
+    t0 = time.perf_counter()
+    T, F = oracle.run(d, T, F, n)
+    el = time.perf_counter() - t0
+    n_total = n + 1
+    el_total = el + one
+    return {"value": sc.ndof * n_total / el_total, "unit": "DOF-steps/s", "cores": threads,
+            "kind": "oracle",
+            "sample": f"{sc.nel_x}x{sc.nel_y} p={sc.p} Strang-CN FP64, first {n_total} of "
+                      f"{sc.steps} steps ({el_total:.1f} s, {threads} OpenMP threads)"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py: this stepper runs on one GPU; multi-GPU runs are not part of this "
+              "build (ensemble members would shard across GPUs with no exchange)", file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    from paper_2604_19370_amd import iga, inputs
+
+    sc = inputs.regional_strang(seed=1, nel=args.nel, steps=args.steps)
+    res = {}
+    ktimes = {}
+    for prec in ("fp32", "fp64"):
+        pl = iga.Plan.from_scenario(sc, precision=prec)
+        pl.factor()
+        wall, ev, T, F = time_steps(pl, sc, args.steps, args.warmup, torch)
+        res[prec] = dict(wall=wall, ev=ev, dofs=sc.ndof * args.steps / wall,
+                         sched=[pl.schedule(0), pl.schedule(1)])
+        ktimes[prec] = kernel_times(pl, sc, args.kernel_reps, torch)
+        pl.close()
+
+    # dominant kernel of the FP32 step: the S1 assembly (time share printed below)
+    w = 4
+    kt = ktimes["fp32"]
+    ndof = sc.ndof
+    nel = sc.nel_x * sc.nel_y
+    dom = max(kt, key=kt.get)
+    # algorithmic bytes of the S1 assembly: read T and fuel, write R and R_fuel
+    alg_bytes = {"assemble_s1_fuel": 4 * w * ndof, "assemble_s3": 3 * w * ndof,
+                 "sweep_x_A": 2 * w * ndof, "sweep_y_M": 2 * w * ndof, "sweep_y_cn": 2 * w * ndof}
+    achieved = alg_bytes[dom] / kt[dom] / 1e9
+    roof = {"kernel": dom, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+            "avg_us": round(kt[dom] * 1e6, 2),
+            "kernel_us": {k: round(v * 1e6, 2) for k, v in kt.items()}}
+
+    line = {
+        "metric": "DOF-steps/s at 1024^2 quadratic IGA (Strang-CN), FP32+refine; FP64 beside",
+        "value": round(res["fp32"]["dofs"], 1),
+        "unit": "DOF-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(res["fp32"]["wall"] / args.steps * 1e3, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 (1D LU and refinement residual f64)",
+        "data": "synthetic",
+        "config": {"workload": f"regional Strang-CN {sc.nel_x}x{sc.nel_y} quadratic, dt 5e-4",
+                   "dofs": ndof, "elements": nel, "steps": args.steps},
+        "fp64": {"value": round(res["fp64"]["dofs"], 1),
+                 "ms_per_step": round(res["fp64"]["wall"] / args.steps * 1e3, 5),
+                 "kernel_us": {k: round(v * 1e6, 2) for k, v in ktimes["fp64"].items()}},
+        "fp32_over_fp64": round(res["fp32"]["dofs"] / res["fp64"]["dofs"], 3),
+        "roofline": roof,
+        "schedules": res["fp32"]["sched"],
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(sc, args.cpu_seconds)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

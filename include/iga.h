@@ -1,0 +1,189 @@
+/*
+ * iga.h -- C ABI of the MI355X (gfx950) quasi-implicit alternating-direction
+ * isogeometric wildfire stepper.
+ *
+ * Method (arXiv 2604.19370): the temperature T and the fuel fraction are
+ * spline coefficient arrays on a tensor-product B-spline space of degree p
+ * with uniform open knots (Section 3.1).  Each time step is a
+ * Peaceman-Rachford step (Section 3.1, eq. PR / eq. matrixPR) or a Strang
+ * splitting step with Crank-Nicolson substeps (Section 3.2, eq. CN /
+ * eq. matrixCN).  Every substep with explicit terms assembles a right-hand
+ * side by Gauss quadrature on the elements -- the non-linear diffusion
+ * C_nld T^3 grad T, the ignition source C_ign [T > T_ig and fuel > thr]
+ * T exp(-T_act / T), forcing and T^4 radiation, the explicit part of the
+ * linear operator and the non-constant part of the wind (generic equation at
+ * the start of Section 3) -- and then solves a Kronecker-product system
+ * (A (x) B) X = R as independent banded 1D systems along x, then along y
+ * (Section 4).  The fuel is consumed explicitly once per step and L2-projected
+ * (the compute_rhs listing of Section 7).
+ *
+ * Conventions shared by every entry point
+ *  - Field layout: dof (i, j), i the x index in [0, Nx), j the y index in
+ *    [0, Ny), Nx = nel_x + p, Ny = nel_y + p, is element i * Ny + j of a dense
+ *    row-major array (the ordering on which A^x (x) A^y acts with the x factor
+ *    on the slow index).  Element type: double for IGA_FP64 plans, float for
+ *    IGA_FP32_REFINE plans.  Every field pointer is a device pointer, 16-byte
+ *    aligned, owned by the caller; the library never frees it and never keeps
+ *    it past the call, except that iga_run keeps a captured HIP graph bound to
+ *    the (T, fuel) pair it was last called with (re-captured when they change).
+ *  - Streams: `stream` is a hipStream_t (NULL = the legacy default stream).
+ *    Every call only enqueues work on that stream and returns; nothing
+ *    synchronises unless stated.  A plan must not be used from two streams at
+ *    once (it owns scratch buffers).
+ *  - Errors: every function returns an iga_status.  IGA_EINVAL is returned
+ *    synchronously for bad arguments before any work is enqueued; HIP runtime
+ *    failures return IGA_EDEVICE.  iga_last_error() returns a description of
+ *    the most recent failure on the calling thread.
+ */
+#ifndef IGA_H
+#define IGA_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    IGA_OK = 0,
+    IGA_EINVAL = 1,       /* invalid argument or descriptor                 */
+    IGA_ENOMEM = 2,       /* device or host allocation failed               */
+    IGA_EDEVICE = 3,      /* a HIP runtime call or kernel launch failed     */
+    IGA_ENONFINITE = 4,   /* iga_run found a NaN/Inf in the state            */
+    IGA_EUNSUPPORTED = 5, /* valid request this build does not implement    */
+    IGA_ESTATE = 6        /* call out of order (e.g. step before factor)    */
+} iga_status;
+
+typedef enum { IGA_PR = 0, IGA_STRANG_CN = 1 } iga_scheme;
+
+/* IGA_FP64: every kernel in double.
+ * IGA_FP32_REFINE: state, right-hand sides and line solves in float with float
+ * accumulation; the 1D LU factorisations are computed in double, and each 1D
+ * solve is followed by one step of iterative refinement whose residual
+ * b - A x0 is formed in double with the double operator. */
+typedef enum { IGA_FP64 = 0, IGA_FP32_REFINE = 1 } iga_precision;
+
+typedef enum { IGA_WIND_CONST = 0, IGA_WIND_SINCOS = 1 } iga_wind_kind;
+
+/* Coefficients of the generic equation at the start of Section 3:
+ *   dT/dt + c_adv b.grad T - c_diff lap T - c_react T - div(c_nld T^3 grad T)
+ *     = c_ign [T > t_ig and fuel > fuel_thr] T exp(-t_act/T) + c_forcing - c_rad T^4
+ * and the fuel consumption of the compute_rhs listing (Section 7):
+ *   d fuel/dt = -fuel_rate [T > t_ig and fuel > fuel_thr] T exp(-t_act/T) fuel. */
+typedef struct {
+    double c_adv, c_diff, c_react, c_nld, c_ign;
+    double t_ig, fuel_thr, t_act;
+    double c_forcing, c_rad, fuel_rate;
+} iga_coeffs;
+
+/* Wind b(x, y):  CONST:  (bx, by)
+ *                SINCOS: (bx + ax sin(2 pi y / len_y), by + ay cos(2 pi x / len_x)).
+ * (bbar_x, bbar_y) is the constant part kept inside the implicit 1D operators
+ * (the G matrices of eq. matrixPR / matrixCN); b - bbar is treated explicitly. */
+typedef struct {
+    int32_t kind;
+    double bx, by, ax, ay;
+    double bbar_x, bbar_y;
+} iga_wind;
+
+typedef struct {
+    int32_t nel_x, nel_y;   /* elements per direction, >= 2p+1 and <= 65536     */
+    int32_t p;              /* B-spline degree, 2 or 3                            */
+    double len_x, len_y;    /* physical edge lengths (m), > 0                     */
+    double dt;              /* time step tau (s), > 0                             */
+    int32_t scheme;         /* iga_scheme                                         */
+    int32_t precision;      /* iga_precision                                      */
+    iga_coeffs c;
+    iga_wind wind;
+    int32_t check_every;    /* iga_run: test the state for NaN/Inf every k steps  */
+                            /* (0 = never; > 0 makes iga_run synchronise)         */
+} iga_plan_desc;
+
+typedef struct iga_plan iga_plan;   /* opaque; owned by the library */
+
+/* Section 2.2 parameter table divided by rho c_p (c_p = 1, rho = 1.293, ...),
+ * with the reaction-rate scale A_r = 1.5e-4 and M/M1 = 1 that the paper
+ * leaves unspecified.  Never fails. */
+void iga_default_coeffs(iga_coeffs *out);
+
+/* Build a plan: knots, Gauss rules, basis tables at the quadrature points, the
+ * 1D matrices M, K, G (Section 3.1) and the directional operators of the
+ * scheme, uploaded to the current HIP device.  Allocates device memory (tables
+ * and scratch of about 2 fields).  *out is NULL on failure.
+ * Errors: IGA_EINVAL (NULL pointers, p not in {2,3}, nel < 2p+1, lengths or dt
+ * not > 0, unknown enum), IGA_ENOMEM, IGA_EDEVICE. */
+iga_status iga_plan_create(const iga_plan_desc *desc, iga_plan **out);
+
+/* Release a plan and everything it owns (synchronises the device first).
+ * NULL is accepted. */
+iga_status iga_plan_destroy(iga_plan *plan);
+
+/* Sizes: Nx, Ny (dofs per direction) and the number of dofs. */
+iga_status iga_plan_dims(const iga_plan *plan, int64_t *nx, int64_t *ny, int64_t *ndof);
+
+/* Factor every banded 1D operator of the plan (eq. matrixPR / matrixCN, the
+ * banded structure of Section 4) with a banded LU without pivoting, in double,
+ * on the device; also precomputes the chunk-transfer tables the line solves
+ * use, and the float copies for IGA_FP32_REFINE plans.  Must be called once
+ * before any solve; enqueued on `stream`. */
+iga_status iga_factor_1d(iga_plan *plan, void *stream);
+
+/* Quadrature right-hand side of one substep (weak forms eq. varPR_wildfire
+ * and eq. varCN).  substep: PR 0 (x implicit) or 1 (y implicit); Strang 0 (S1)
+ * or 2 (S3).  Reads T and fuel, writes rhs_T; when rhs_fuel is not NULL also
+ * writes the fuel right-hand side fuel v - tau fuel_rate [ign] T exp(-t_act/T)
+ * fuel v.  All four are fields (layout above); rhs buffers must not alias the
+ * inputs.  The Strang middle substep has no quadrature right-hand side (it is
+ * iga_line_solve(dir = 1, which = 2)): substep 1 of a Strang plan is
+ * IGA_EINVAL. */
+iga_status iga_assemble_rhs(const iga_plan *plan, int32_t substep, const void *T,
+                            const void *fuel, void *rhs_T, void *rhs_fuel, void *stream);
+
+/* In-place line solve on the field x along direction dir (0 = x: Ny lines of
+ * length Nx; 1 = y: Nx lines of length Ny) -- one factor of the Kronecker
+ * solve (A (x) B)^{-1} = (A^{-1} (x) I)(I (x) B^{-1}) of Section 4:
+ *   which 0: x <- A^{-1} x  with A the scheme's implicit operator in dir
+ *            (PR: (1 - tau/2 c_react) M + tau/2 (c_diff K + c_adv bbar G) along
+ *            x, M + tau/2 (...) along y; Strang: tau/4 and reaction along x,
+ *            tau/2 along y);
+ *   which 1: x <- M^{-1} x;
+ *   which 2: x <- A^{-1} B x with B the explicit Crank-Nicolson counterpart of
+ *            A (signs of the tau terms flipped) -- the Strang middle substep.
+ * Requires iga_factor_1d. */
+iga_status iga_line_solve(const iga_plan *plan, int32_t dir, int32_t which, void *x,
+                          void *stream);
+
+/* One full time step, in place on (T, fuel): PR = assemble, A^x (x) M^y solve,
+ * assemble, M^x (x) A^y solve; Strang-CN = S1 (assemble, A^x (x) M^y), S2
+ * (A^{-1} B along y), S3 (assemble, A^x (x) M^y); then the fuel update
+ * (Mx (x) My)^{-1} R_fuel(T^n, fuel^n).  Requires iga_factor_1d. */
+iga_status iga_step(iga_plan *plan, void *T, void *fuel, void *stream);
+
+/* nsteps steps, in place, replayed from a HIP graph captured on first use for
+ * this (T, fuel) pair.  With desc.check_every > 0 the state is tested for
+ * NaN/Inf every check_every steps (this synchronises `stream`) and
+ * IGA_ENONFINITE is returned at the first failure (state left as computed). */
+iga_status iga_run(iga_plan *plan, void *T, void *fuel, int64_t nsteps, void *stream);
+
+/* Line-solve schedule chosen for direction dir: lines per wavefront `lw`,
+ * rows per lane `m`, chunks per line `chunks`, waves per workgroup `waves`. */
+iga_status iga_plan_schedule(const iga_plan *plan, int32_t dir, int32_t *lw, int32_t *m,
+                             int32_t *chunks, int32_t *waves);
+
+/* Choose a different line-solve schedule for direction dir (autotuning).
+ * lw in {64, 16, 8}; waves in {4, 8, 16}; the rows per lane follow from the
+ * line length.  Re-derives the chunk tables on `stream` if already factored.
+ * IGA_EUNSUPPORTED if the combination is not compiled or does not fit. */
+iga_status iga_plan_set_schedule(iga_plan *plan, int32_t dir, int32_t lw, int32_t waves,
+                                 void *stream);
+
+/* Assembly schedule: element rows marched per wavefront (>= 1). */
+iga_status iga_plan_set_assembly_rows(iga_plan *plan, int32_t rows);
+
+/* Thread-local description of the last error ("" if none). */
+const char *iga_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* IGA_H */

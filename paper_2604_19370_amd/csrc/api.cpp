@@ -1,0 +1,350 @@
+// api.cpp -- the C ABI (include/iga.h): argument checking, the step
+// sequences of the two schemes, and the graph-replayed run loop.
+#include <cmath>
+#include <cstring>
+#include <new>
+
+#include "iga_internal.h"
+
+namespace iga {
+
+static thread_local std::string g_error;
+
+void set_error(const std::string &msg) { g_error = msg; }
+
+iga_status fail(iga_status st, const std::string &msg)
+{
+    g_error = msg;
+    return st;
+}
+
+iga_status hip_fail(hipError_t e, const char *what)
+{
+    g_error = std::string(what) + ": " + hipGetErrorString(e);
+    return e == hipErrorOutOfMemory ? IGA_ENOMEM : IGA_EDEVICE;
+}
+
+void GraphEntry::reset()
+{
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    exec = nullptr;
+    graph = nullptr;
+    T = fuel = nullptr;
+    steps = 0;
+}
+
+static bool aligned(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; }
+
+static iga_status check_desc(const iga_plan_desc *d)
+{
+    if (!d) return fail(IGA_EINVAL, "desc is NULL");
+    if (d->p != 2 && d->p != 3) return fail(IGA_EINVAL, "p must be 2 or 3");
+    if (d->nel_x < 2 * d->p + 1 || d->nel_y < 2 * d->p + 1)
+        return fail(IGA_EINVAL, "nel_x and nel_y must be >= 2p+1");
+    if (d->nel_x > 65536 || d->nel_y > 65536) return fail(IGA_EINVAL, "nel above 65536");
+    if (!(d->len_x > 0) || !(d->len_y > 0) || !std::isfinite(d->len_x) || !std::isfinite(d->len_y))
+        return fail(IGA_EINVAL, "lengths must be finite and > 0");
+    if (!(d->dt > 0) || !std::isfinite(d->dt)) return fail(IGA_EINVAL, "dt must be finite and > 0");
+    if (d->scheme != IGA_PR && d->scheme != IGA_STRANG_CN) return fail(IGA_EINVAL, "unknown scheme");
+    if (d->precision != IGA_FP64 && d->precision != IGA_FP32_REFINE)
+        return fail(IGA_EINVAL, "unknown precision");
+    if (d->wind.kind != IGA_WIND_CONST && d->wind.kind != IGA_WIND_SINCOS)
+        return fail(IGA_EINVAL, "unknown wind kind");
+    if (d->check_every < 0) return fail(IGA_EINVAL, "check_every must be >= 0");
+    const double *c = &d->c.c_adv;
+    for (int i = 0; i < 11; ++i)
+        if (!std::isfinite(c[i])) return fail(IGA_EINVAL, "non-finite coefficient");
+    if (!(d->c.t_act > 0)) return fail(IGA_EINVAL, "t_act must be > 0");
+    return IGA_OK;
+}
+
+static iga_status check_field(const void *p, const char *name)
+{
+    if (!p) return fail(IGA_EINVAL, std::string(name) + " is NULL");
+    if (!aligned(p)) return fail(IGA_EINVAL, std::string(name) + " is not 16-byte aligned");
+    return IGA_OK;
+}
+
+// One step in place; the right-hand sides live in the plan's scratch buffers.
+static iga_status step_impl(iga_plan *pl, void *T, void *fuel, hipStream_t s)
+{
+    void *R = pl->scratch_r.ptr, *RF = pl->scratch_rf.ptr;
+    iga_status st;
+    const bool pr = pl->d.scheme == IGA_PR;
+    // substep 1 (PR: x implicit; Strang: S1) + the fuel right-hand side
+    if ((st = launch_assemble(pl, 0, T, fuel, R, RF, s))) return st;
+    SweepJob jx[2] = {{R, R, OP_AX, -1, -1}, {RF, RF, OP_MX, -1, -1}};
+    if ((st = launch_sweep(pl, 0, jx, 2, s))) return st;
+    if (pr) {
+        SweepJob jy[1] = {{R, T, OP_MY, -1, -1}};
+        if ((st = launch_sweep(pl, 1, jy, 1, s))) return st;
+        // substep 2: y implicit
+        if ((st = launch_assemble(pl, 1, T, fuel, R, nullptr, s))) return st;
+        SweepJob jx2[1] = {{R, R, OP_MX, -1, -1}};
+        if ((st = launch_sweep(pl, 0, jx2, 1, s))) return st;
+        SweepJob jy2[2] = {{R, T, OP_AY, -1, -1}, {RF, fuel, OP_MY, -1, -1}};
+        if ((st = launch_sweep(pl, 1, jy2, 2, s))) return st;
+    } else {
+        // S1's y solve fused with S2: T** = (A^y)^{-1} B^y (M^y)^{-1} R along y
+        SweepJob jy[1] = {{R, T, OP_MY, BAND_BY, OP_AY}};
+        if ((st = launch_sweep(pl, 1, jy, 1, s))) return st;
+        // S3
+        if ((st = launch_assemble(pl, 2, T, fuel, R, nullptr, s))) return st;
+        SweepJob jx2[1] = {{R, R, OP_AX, -1, -1}};
+        if ((st = launch_sweep(pl, 0, jx2, 1, s))) return st;
+        SweepJob jy2[2] = {{R, T, OP_MY, -1, -1}, {RF, fuel, OP_MY, -1, -1}};
+        if ((st = launch_sweep(pl, 1, jy2, 2, s))) return st;
+    }
+    return IGA_OK;
+}
+
+
+// Capture `steps` steps on a private stream into g (kernels only; no memset
+// or host callbacks are recorded).
+static iga_status capture(iga_plan *pl, GraphEntry &g, void *T, void *fuel, int64_t steps)
+{
+    if (g.exec && g.T == T && g.fuel == fuel && g.steps == steps) return IGA_OK;
+    g.reset();
+    hipStream_t cs;
+    IGA_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+    hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) {
+        (void)hipStreamDestroy(cs);
+        return hip_fail(e, "hipStreamBeginCapture");
+    }
+    iga_status cst = IGA_OK;
+    for (int64_t k = 0; k < steps && !cst; ++k) cst = step_impl(pl, T, fuel, cs);
+    hipGraph_t graph = nullptr;
+    e = hipStreamEndCapture(cs, &graph);
+    (void)hipStreamDestroy(cs);
+    if (cst) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return cst;
+    }
+    if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+    hipGraphExec_t exec = nullptr;
+    e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        (void)hipGraphDestroy(graph);
+        return hip_fail(e, "hipGraphInstantiate");
+    }
+    g.graph = graph;
+    g.exec = exec;
+    g.T = T;
+    g.fuel = fuel;
+    g.steps = steps;
+    return IGA_OK;
+}
+
+}  // namespace iga
+
+using namespace iga;
+
+extern "C" {
+
+const char *iga_last_error(void) { return g_error.c_str(); }
+
+void iga_default_coeffs(iga_coeffs *out)
+{
+    if (!out) return;
+    // Table of Section 2.2, every term divided by rho c_p
+    const double cp = 1.0, rho = 1.293, kappa = 0.3, sigma = 5.67e-8, emis = 0.05;
+    const double ch = 1.0, hc = -70.0, cw = 0.5, chi = 2e-2, t_amb = 300.0;
+    const double dx = 3.5e-2 / emis, dz = 1.5 * emis;
+    const double a_r = 1.5e-4, m_over_m1 = 1.0;  // not given in the paper
+    const double rc = rho * cp;
+    out->c_adv = cw;
+    out->c_diff = kappa / rc;
+    out->c_react = -chi / rc;
+    out->c_nld = 4.0 * sigma * emis * dx / rc;
+    out->c_rad = sigma * emis / dz / rc;
+    out->c_forcing = (chi * t_amb + sigma * emis / dz * t_amb * t_amb * t_amb * t_amb) / rc;
+    out->c_ign = 1e4 * ch * (-hc) * m_over_m1 * a_r / cp;
+    out->t_ig = 800.0;
+    out->fuel_thr = 0.2;
+    out->t_act = 300.0;
+    out->fuel_rate = 300.0 * a_r;
+}
+
+iga_status iga_plan_create(const iga_plan_desc *desc, iga_plan **out)
+{
+    if (!out) return fail(IGA_EINVAL, "out is NULL");
+    *out = nullptr;
+    iga_status st = check_desc(desc);
+    if (st) return st;
+    iga_plan *pl = new (std::nothrow) iga_plan();
+    if (!pl) return fail(IGA_ENOMEM, "host allocation failed");
+    try {
+        pl->d = *desc;
+        if ((st = build_plan_host(pl)) || (st = upload_plan(pl)) ||
+            (st = choose_schedule(pl, 0, 0, 0)) || (st = choose_schedule(pl, 1, 0, 0))) {
+            delete pl;
+            return st;
+        }
+        pl->asm_rows = pl->Nx >= 2048 ? 64 : (pl->Nx >= 512 ? 32 : 16);
+    } catch (const std::bad_alloc &) {
+        delete pl;
+        return fail(IGA_ENOMEM, "host allocation failed");
+    }
+    *out = pl;
+    return IGA_OK;
+}
+
+iga_status iga_plan_destroy(iga_plan *plan)
+{
+    if (!plan) return IGA_OK;
+    (void)hipDeviceSynchronize();
+    plan->graph.reset();
+    delete plan;
+    return IGA_OK;
+}
+
+iga_status iga_plan_dims(const iga_plan *plan, int64_t *nx, int64_t *ny, int64_t *ndof)
+{
+    if (!plan) return fail(IGA_EINVAL, "plan is NULL");
+    if (nx) *nx = plan->Nx;
+    if (ny) *ny = plan->Ny;
+    if (ndof) *ndof = (int64_t)plan->ndof;
+    return IGA_OK;
+}
+
+iga_status iga_factor_1d(iga_plan *plan, void *stream)
+{
+    if (!plan) return fail(IGA_EINVAL, "plan is NULL");
+    iga_status st = launch_factor(plan, static_cast<hipStream_t>(stream));
+    if (st) return st;
+    plan->factored = true;
+    plan->graph.reset();
+    return IGA_OK;
+}
+
+iga_status iga_assemble_rhs(const iga_plan *plan, int32_t substep, const void *T, const void *fuel,
+                            void *rhs_T, void *rhs_fuel, void *stream)
+{
+    if (!plan) return fail(IGA_EINVAL, "plan is NULL");
+    iga_status st;
+    if ((st = check_field(T, "T")) || (st = check_field(fuel, "fuel")) ||
+        (st = check_field(rhs_T, "rhs_T")))
+        return st;
+    if (rhs_fuel && !aligned(rhs_fuel)) return fail(IGA_EINVAL, "rhs_fuel is not 16-byte aligned");
+    if (rhs_T == T || rhs_T == fuel || (rhs_fuel && (rhs_fuel == T || rhs_fuel == fuel)))
+        return fail(IGA_EINVAL, "right-hand sides must not alias the state");
+    if (plan->d.scheme == IGA_PR) {
+        if (substep != 0 && substep != 1) return fail(IGA_EINVAL, "PR substep must be 0 or 1");
+    } else if (substep != 0 && substep != 2) {
+        return fail(IGA_EINVAL,
+                    "Strang substep must be 0 or 2 (the middle substep is iga_line_solve(1, 2))");
+    }
+    return launch_assemble(plan, substep, T, fuel, rhs_T, rhs_fuel, static_cast<hipStream_t>(stream));
+}
+
+iga_status iga_line_solve(const iga_plan *plan, int32_t dir, int32_t which, void *x, void *stream)
+{
+    if (!plan) return fail(IGA_EINVAL, "plan is NULL");
+    if (dir != 0 && dir != 1) return fail(IGA_EINVAL, "dir must be 0 or 1");
+    if (which < 0 || which > 2) return fail(IGA_EINVAL, "which must be 0, 1 or 2");
+    iga_status st = check_field(x, "x");
+    if (st) return st;
+    if (!plan->factored) return fail(IGA_ESTATE, "iga_factor_1d has not been called");
+    SweepJob j;
+    j.src = x;
+    j.dst = x;
+    const int A = dir ? OP_AY : OP_AX, M = dir ? OP_MY : OP_MX;
+    if (which == 0) j = {x, x, A, -1, -1};
+    else if (which == 1) j = {x, x, M, -1, -1};
+    else j = {x, x, -1, dir ? BAND_BY : BAND_BX, A};
+    return launch_sweep(plan, dir, &j, 1, static_cast<hipStream_t>(stream));
+}
+
+iga_status iga_step(iga_plan *plan, void *T, void *fuel, void *stream)
+{
+    if (!plan) return fail(IGA_EINVAL, "plan is NULL");
+    iga_status st;
+    if ((st = check_field(T, "T")) || (st = check_field(fuel, "fuel"))) return st;
+    if (T == fuel) return fail(IGA_EINVAL, "T and fuel must be different buffers");
+    if (!plan->factored) return fail(IGA_ESTATE, "iga_factor_1d has not been called");
+    return step_impl(plan, T, fuel, static_cast<hipStream_t>(stream));
+}
+
+iga_status iga_run(iga_plan *plan, void *T, void *fuel, int64_t nsteps, void *stream)
+{
+    if (!plan) return fail(IGA_EINVAL, "plan is NULL");
+    iga_status st;
+    if ((st = check_field(T, "T")) || (st = check_field(fuel, "fuel"))) return st;
+    if (T == fuel) return fail(IGA_EINVAL, "T and fuel must be different buffers");
+    if (nsteps < 0) return fail(IGA_EINVAL, "nsteps must be >= 0");
+    if (!plan->factored) return fail(IGA_ESTATE, "iga_factor_1d has not been called");
+    if (nsteps == 0) return IGA_OK;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    // graph of `chunk` steps replayed; a tail graph for the remainder
+    const int64_t chunk = plan->d.check_every > 0 ? std::min<int64_t>(plan->d.check_every, nsteps)
+                                                  : std::min<int64_t>(nsteps, 256);
+    const int64_t tail = nsteps % chunk;
+    if ((st = capture(plan, plan->graph.main, T, fuel, chunk))) return st;
+    if (tail && (st = capture(plan, plan->graph.tail, T, fuel, tail))) return st;
+    int *flag = plan->flag.as<int>();
+    int64_t done = 0;
+    while (done < nsteps) {
+        const int64_t k = std::min<int64_t>(chunk, nsteps - done);
+        IGA_HIP(hipGraphLaunch(k == chunk ? plan->graph.main.exec : plan->graph.tail.exec, s));
+        done += k;
+        if (plan->d.check_every > 0) {
+            IGA_HIP(hipMemsetAsync(flag, 0, sizeof(int), s));
+            if ((st = launch_nonfinite(plan, T, fuel, flag, s))) return st;
+            int h = 0;
+            IGA_HIP(hipMemcpyAsync(&h, flag, sizeof(int), hipMemcpyDeviceToHost, s));
+            IGA_HIP(hipStreamSynchronize(s));
+            if (h) return fail(IGA_ENONFINITE, "non-finite value after step " + std::to_string(done));
+        }
+    }
+    return IGA_OK;
+}
+
+iga_status iga_plan_schedule(const iga_plan *plan, int32_t dir, int32_t *lw, int32_t *m,
+                             int32_t *chunks, int32_t *waves)
+{
+    if (!plan) return fail(IGA_EINVAL, "plan is NULL");
+    if (dir != 0 && dir != 1) return fail(IGA_EINVAL, "dir must be 0 or 1");
+    const Schedule &sc = plan->sched[dir];
+    if (lw) *lw = sc.lw;
+    if (m) *m = sc.m;
+    if (chunks) *chunks = sc.chunks;
+    if (waves) *waves = sc.waves;
+    return IGA_OK;
+}
+
+iga_status iga_plan_set_schedule(iga_plan *plan, int32_t dir, int32_t lw, int32_t waves, void *stream)
+{
+    if (!plan) return fail(IGA_EINVAL, "plan is NULL");
+    if (dir != 0 && dir != 1) return fail(IGA_EINVAL, "dir must be 0 or 1");
+    if (lw != 64 && lw != 16 && lw != 8) return fail(IGA_EINVAL, "lw must be 64, 16 or 8");
+    if (waves != 4 && waves != 8 && waves != 16) return fail(IGA_EINVAL, "waves must be 4, 8 or 16");
+    Schedule old = plan->sched[dir];
+    iga_status st = choose_schedule(plan, dir, lw, waves);
+    if (st) {
+        plan->sched[dir] = old;
+        return st;
+    }
+    plan->graph.reset();
+    if (plan->factored) {
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        for (int op = 0; op < NOPS; ++op) {
+            if (((op == OP_AX || op == OP_MX) ? 0 : 1) != dir) continue;
+            if ((st = launch_chunk_tables(plan, op, s))) return st;
+        }
+        IGA_HIP(hipStreamSynchronize(s));
+    }
+    return IGA_OK;
+}
+
+iga_status iga_plan_set_assembly_rows(iga_plan *plan, int32_t rows)
+{
+    if (!plan) return fail(IGA_EINVAL, "plan is NULL");
+    if (rows < 1) return fail(IGA_EINVAL, "rows must be >= 1");
+    plan->asm_rows = rows;
+    plan->graph.reset();
+    return IGA_OK;
+}
+
+}  // extern "C"

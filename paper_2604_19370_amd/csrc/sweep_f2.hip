@@ -1,0 +1,6 @@
+// sweep_f2.hip -- line-solve kernels for float state, degree 2.
+#include "sweep_kernels.h"
+
+namespace iga {
+SweepFn pick_sweep_f2(int lw, int mm, bool diry) { return pick_lw_mm<float, 2>(lw, mm, diry); }
+}  // namespace iga

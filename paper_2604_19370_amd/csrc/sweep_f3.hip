@@ -1,0 +1,6 @@
+// sweep_f3.hip -- line-solve kernels for float state, degree 3.
+#include "sweep_kernels.h"
+
+namespace iga {
+SweepFn pick_sweep_f3(int lw, int mm, bool diry) { return pick_lw_mm<float, 3>(lw, mm, diry); }
+}  // namespace iga

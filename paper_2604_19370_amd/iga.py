@@ -1,0 +1,220 @@
+"""ctypes binding of ``libiga.so`` (the C ABI declared in ``include/iga.h``).
+
+Argument marshalling only: every step of the stepper runs in the HIP library.
+The library is loaded on first use; if it is missing the call raises -- there
+is no fallback.  PyTorch is used for device memory and streams: fields are
+``torch.Tensor`` objects on a HIP device (float64 for FP64 plans, float32 for
+FP32-with-refinement plans) of shape ``(Nx, Ny)``, C-contiguous.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libiga.so")
+
+OK, EINVAL, ENOMEM, EDEVICE, ENONFINITE, EUNSUPPORTED, ESTATE = range(7)
+PR, STRANG_CN = 0, 1
+FP64, FP32_REFINE = 0, 1
+WIND_CONST, WIND_SINCOS = 0, 1
+
+EXPORTED = ("iga_default_coeffs", "iga_plan_create", "iga_plan_destroy", "iga_plan_dims",
+            "iga_factor_1d", "iga_assemble_rhs", "iga_line_solve", "iga_step", "iga_run",
+            "iga_plan_schedule", "iga_plan_set_schedule", "iga_plan_set_assembly_rows",
+            "iga_last_error")
+
+_COEFF_NAMES = ("c_adv", "c_diff", "c_react", "c_nld", "c_ign", "t_ig", "fuel_thr", "t_act",
+                "c_forcing", "c_rad", "fuel_rate")
+
+
+class Coeffs(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_double) for n in _COEFF_NAMES]
+
+
+class Wind(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("bx", ctypes.c_double), ("by", ctypes.c_double),
+                ("ax", ctypes.c_double), ("ay", ctypes.c_double),
+                ("bbar_x", ctypes.c_double), ("bbar_y", ctypes.c_double)]
+
+
+class PlanDesc(ctypes.Structure):
+    _fields_ = [("nel_x", ctypes.c_int32), ("nel_y", ctypes.c_int32), ("p", ctypes.c_int32),
+                ("len_x", ctypes.c_double), ("len_y", ctypes.c_double), ("dt", ctypes.c_double),
+                ("scheme", ctypes.c_int32), ("precision", ctypes.c_int32), ("c", Coeffs),
+                ("wind", Wind), ("check_every", ctypes.c_int32)]
+
+
+class IgaError(RuntimeError):
+    def __init__(self, status: int, what: str, msg: str):
+        super().__init__(f"{what} failed (status {status}): {msg}")
+        self.status = status
+
+
+_lib: Optional[ctypes.CDLL] = None
+
+
+def lib() -> ctypes.CDLL:
+    """Load libiga.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                               "`python -m paper_2604_19370_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
+        L.iga_default_coeffs.argtypes = [ctypes.POINTER(Coeffs)]
+        L.iga_default_coeffs.restype = None
+        L.iga_plan_create.argtypes = [ctypes.POINTER(PlanDesc), ctypes.POINTER(vp)]
+        L.iga_plan_destroy.argtypes = [vp]
+        L.iga_plan_dims.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(i64),
+                                    ctypes.POINTER(i64)]
+        L.iga_factor_1d.argtypes = [vp, vp]
+        L.iga_assemble_rhs.argtypes = [vp, i32, vp, vp, vp, vp, vp]
+        L.iga_line_solve.argtypes = [vp, i32, i32, vp, vp]
+        L.iga_step.argtypes = [vp, vp, vp, vp]
+        L.iga_run.argtypes = [vp, vp, vp, i64, vp]
+        L.iga_plan_schedule.argtypes = [vp, i32] + [ctypes.POINTER(i32)] * 4
+        L.iga_plan_set_schedule.argtypes = [vp, i32, i32, i32, vp]
+        L.iga_plan_set_assembly_rows.argtypes = [vp, i32]
+        L.iga_last_error.argtypes = []
+        L.iga_last_error.restype = ctypes.c_char_p
+        for name in EXPORTED[1:-1]:
+            getattr(L, name).restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def last_error() -> str:
+    return lib().iga_last_error().decode()
+
+
+def _check(status: int, what: str):
+    if status != OK:
+        raise IgaError(status, what, last_error())
+
+
+def default_coeffs() -> dict:
+    c = Coeffs()
+    lib().iga_default_coeffs(ctypes.byref(c))
+    return {n: getattr(c, n) for n in _COEFF_NAMES}
+
+
+def make_desc(nel_x, nel_y, p, len_x, len_y, dt, scheme, precision="fp64", wind=None,
+              coeffs=None, check_every=0) -> PlanDesc:
+    d = PlanDesc()
+    d.nel_x, d.nel_y, d.p = int(nel_x), int(nel_y), int(p)
+    d.len_x, d.len_y, d.dt = float(len_x), float(len_y), float(dt)
+    d.scheme = {"pr": PR, "strang": STRANG_CN}.get(scheme, scheme)
+    d.precision = {"fp64": FP64, "fp32": FP32_REFINE, "fp32_refine": FP32_REFINE}.get(precision,
+                                                                                      precision)
+    co = default_coeffs()
+    if coeffs:
+        co.update(coeffs)
+    for n in _COEFF_NAMES:
+        setattr(d.c, n, float(co[n]))
+    w = dict(kind="const", bx=0.0, by=0.0, ax=0.0, ay=0.0, bbar_x=None, bbar_y=None)
+    if wind:
+        w.update(wind)
+    d.wind.kind = {"const": WIND_CONST, "sincos": WIND_SINCOS}.get(w["kind"], w["kind"])
+    d.wind.bx, d.wind.by = float(w["bx"]), float(w["by"])
+    d.wind.ax, d.wind.ay = float(w["ax"]), float(w["ay"])
+    d.wind.bbar_x = float(w["bx"] if w["bbar_x"] is None else w["bbar_x"])
+    d.wind.bbar_y = float(w["by"] if w["bbar_y"] is None else w["bbar_y"])
+    d.check_every = int(check_every)
+    return d
+
+
+def _ptr(t) -> ctypes.c_void_p:
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream) -> ctypes.c_void_p:
+    if stream is None:
+        import torch
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(int(stream.cuda_stream))
+
+
+class Plan:
+    """An iga_plan (knots, quadrature tables, factored 1D operators, scratch)."""
+
+    def __init__(self, desc: PlanDesc):
+        self.desc = desc
+        h = ctypes.c_void_p()
+        _check(lib().iga_plan_create(ctypes.byref(desc), ctypes.byref(h)), "iga_plan_create")
+        self._h = h
+        nx, ny, nd = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+        _check(lib().iga_plan_dims(h, ctypes.byref(nx), ctypes.byref(ny), ctypes.byref(nd)),
+               "iga_plan_dims")
+        self.Nx, self.Ny, self.ndof = nx.value, ny.value, nd.value
+        self.fp32 = desc.precision == FP32_REFINE
+
+    @classmethod
+    def from_scenario(cls, sc, precision="fp64", coeffs=None, check_every=0) -> "Plan":
+        return cls(make_desc(sc.nel_x, sc.nel_y, sc.p, sc.len_x, sc.len_y, sc.dt, sc.scheme,
+                             precision=precision, wind=sc.wind_dict(), coeffs=coeffs,
+                             check_every=check_every))
+
+    @property
+    def handle(self):
+        return self._h
+
+    @property
+    def dtype(self):
+        import torch
+        return torch.float32 if self.fp32 else torch.float64
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().iga_plan_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _field(self, t, name):
+        if t.dtype != self.dtype or not t.is_contiguous() or tuple(t.shape) != (self.Nx, self.Ny):
+            raise ValueError(f"{name}: expected contiguous {self.dtype} tensor of shape "
+                             f"({self.Nx}, {self.Ny}), got {t.dtype} {tuple(t.shape)}")
+        if t.device.type != "cuda":
+            raise ValueError(f"{name} must be on the GPU")
+        return _ptr(t)
+
+    def factor(self, stream=None):
+        _check(lib().iga_factor_1d(self._h, _stream(stream)), "iga_factor_1d")
+
+    def assemble_rhs(self, substep, T, fuel, rhs_T, rhs_fuel=None, stream=None):
+        _check(lib().iga_assemble_rhs(self._h, int(substep), self._field(T, "T"),
+                                      self._field(fuel, "fuel"), self._field(rhs_T, "rhs_T"),
+                                      self._field(rhs_fuel, "rhs_fuel") if rhs_fuel is not None
+                                      else None, _stream(stream)), "iga_assemble_rhs")
+
+    def line_solve(self, dir, which, x, stream=None):
+        _check(lib().iga_line_solve(self._h, int(dir), int(which), self._field(x, "x"),
+                                    _stream(stream)), "iga_line_solve")
+
+    def step(self, T, fuel, stream=None):
+        _check(lib().iga_step(self._h, self._field(T, "T"), self._field(fuel, "fuel"),
+                              _stream(stream)), "iga_step")
+
+    def run(self, T, fuel, nsteps, stream=None):
+        _check(lib().iga_run(self._h, self._field(T, "T"), self._field(fuel, "fuel"),
+                             int(nsteps), _stream(stream)), "iga_run")
+
+    def schedule(self, dir):
+        v = [ctypes.c_int32() for _ in range(4)]
+        _check(lib().iga_plan_schedule(self._h, int(dir), *[ctypes.byref(x) for x in v]),
+               "iga_plan_schedule")
+        return dict(lw=v[0].value, m=v[1].value, chunks=v[2].value, waves=v[3].value)
+
+    def set_schedule(self, dir, lw, waves, stream=None):
+        _check(lib().iga_plan_set_schedule(self._h, int(dir), int(lw), int(waves),
+                                           _stream(stream)), "iga_plan_set_schedule")
+
+    def set_assembly_rows(self, rows):
+        _check(lib().iga_plan_set_assembly_rows(self._h, int(rows)), "iga_plan_set_assembly_rows")

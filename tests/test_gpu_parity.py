@@ -1,0 +1,191 @@
+"""Parity of the HIP library (through the C ABI) with the FP64 CPU oracle.
+
+FP64 plans must match the oracle to 1e-12 relative L2 per step (the tolerance
+of the method's double-precision path); FP32-with-refinement plans to 1e-6
+per step.  Cases span several workgroup tiles with ragged tails, both degrees,
+both schemes, every line-solve schedule, the minimum mesh, and edge cases.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2604_19370_amd import iga, inputs
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+TOL64 = 1e-12
+TOL32 = 1e-6
+
+
+def dev(a, fp32=False):
+    return torch.tensor(np.ascontiguousarray(a), dtype=torch.float32 if fp32 else torch.float64,
+                        device="cuda")
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.double().cpu().numpy()
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def plan_and_oracle(sc, precision="fp64", coeffs=None):
+    pl = iga.Plan.from_scenario(sc, precision=precision, coeffs=coeffs)
+    pl.factor()
+    return pl, oracle.desc_from_scenario(sc, coeffs=coeffs)
+
+
+CASES = [
+    # (nel_x, nel_y, p, scheme)
+    (37, 29, 2, "pr"),
+    (29, 61, 2, "strang"),
+    (130, 70, 2, "strang"),
+    (45, 33, 3, "pr"),
+    (71, 40, 3, "strang"),
+    (5, 5, 2, "pr"),       # minimum mesh nel = 2p+1
+    (7, 9, 3, "strang"),   # minimum mesh for p=3
+]
+
+
+@pytest.mark.parametrize("nx,ny,p,scheme", CASES)
+@pytest.mark.parametrize("dir,which", [(0, 0), (0, 1), (1, 0), (1, 1), (1, 2)])
+def test_line_solve_fp64(nx, ny, p, scheme, dir, which):
+    print(f"line_solve fp64 {nx}x{ny} p{p} {scheme} dir{dir} which{which}", flush=True)
+    sc = inputs.small_case(100 + nx, nx, ny, p, scheme)
+    pl, od = plan_and_oracle(sc)
+    X = np.random.default_rng(nx * ny).standard_normal((nx + p, ny + p))
+    x = dev(X)
+    pl.line_solve(dir, which, x)
+    ref = oracle.line_solve(od, dir, which, X)
+    assert rel(host(x), ref) < TOL64
+
+
+@pytest.mark.parametrize("dir", [0, 1])
+@pytest.mark.parametrize("lw,waves", [(64, 4), (64, 8), (64, 16), (16, 4), (16, 8), (16, 16),
+                                      (8, 8), (8, 16)])
+def test_line_solve_every_schedule(dir, lw, waves):
+    print(f"schedule dir{dir} lw{lw} waves{waves}", flush=True)
+    sc = inputs.small_case(7, 150, 133, 2, "strang")
+    for precision, tol in (("fp64", TOL64), ("fp32", TOL32)):
+        pl, od = plan_and_oracle(sc, precision)
+        try:
+            pl.set_schedule(dir, lw, waves)
+        except iga.IgaError as e:
+            assert e.status == iga.EUNSUPPORTED
+            continue
+        X = np.random.default_rng(lw + waves).standard_normal((152, 135))
+        x = dev(X, precision == "fp32")
+        pl.line_solve(dir, 0, x)
+        assert rel(host(x), oracle.line_solve(od, dir, 0, X)) < tol
+
+
+@pytest.mark.parametrize("nx,ny,p,scheme", CASES)
+def test_assemble_fp64(nx, ny, p, scheme):
+    print(f"assemble fp64 {nx}x{ny} p{p} {scheme}", flush=True)
+    sc = inputs.small_case(200 + nx, nx, ny, p, scheme)
+    pl, od = plan_and_oracle(sc)
+    T = sc.T0 + np.random.default_rng(3).uniform(0, 600, sc.T0.shape)
+    for substep in ((0, 1) if scheme == "pr" else (0, 2)):
+        Rref, RFref = oracle.assemble(od, substep, T, sc.fuel0, with_fuel=True)
+        t, f = dev(T), dev(sc.fuel0)
+        r, rf = torch.zeros_like(t), torch.zeros_like(t)
+        pl.assemble_rhs(substep, t, f, r, rf)
+        assert rel(host(r), Rref) < TOL64
+        assert rel(host(rf), RFref) < TOL64
+
+
+@pytest.mark.parametrize("nx,ny,p,scheme", CASES)
+def test_steps_fp64(nx, ny, p, scheme):
+    print(f"steps fp64 {nx}x{ny} p{p} {scheme}", flush=True)
+    sc = inputs.small_case(300 + nx, nx, ny, p, scheme, dt=2e-3)
+    pl, od = plan_and_oracle(sc)
+    T, F = sc.T0.copy(), sc.fuel0.copy()
+    t, f = dev(T), dev(F)
+    for k in range(4):
+        T, F = oracle.step(od, T, F)
+        pl.step(t, f)
+        assert rel(host(t), T) < TOL64, k
+        assert rel(host(f), F) < TOL64, k
+
+
+@pytest.mark.parametrize("nx,ny,p,scheme", CASES[:5])
+def test_steps_fp32_refine(nx, ny, p, scheme):
+    print(f"steps fp32 {nx}x{ny} p{p} {scheme}", flush=True)
+    sc = inputs.small_case(400 + nx, nx, ny, p, scheme, dt=2e-3)
+    pl, od = plan_and_oracle(sc, "fp32")
+    T, F = sc.T0.copy(), sc.fuel0.copy()
+    t, f = dev(T, True), dev(F, True)
+    for k in range(3):
+        T0 = host(t)
+        F0 = host(f)
+        T, F = oracle.step(od, T0, F0)   # one step from the GPU state: per-step error
+        pl.step(t, f)
+        assert rel(host(t), T) < TOL32, k
+        assert rel(host(f), F) < TOL32, k
+
+
+def test_plain_pr_64_twenty_steps_fp64():
+    """64x64 quadratic, PR, dt 1e-3, 20 steps: per-step parity with the oracle."""
+    sc = inputs.plain_pr_64(0)
+    pl, od = plan_and_oracle(sc)
+    T, F = sc.T0.copy(), sc.fuel0.copy()
+    t, f = dev(T), dev(F)
+    for k in range(sc.steps):
+        Tprev, Fprev = host(t), host(f)
+        T, F = oracle.step(od, Tprev, Fprev)
+        pl.step(t, f)
+        assert rel(host(t), T) < TOL64, k
+        assert rel(host(f), F) < TOL64, k
+
+
+def test_run_graph_equals_eager_steps_bitwise():
+    sc = inputs.small_case(9, 90, 70, 2, "strang", dt=2e-3)
+    pl, _ = plan_and_oracle(sc)
+    t1, f1 = dev(sc.T0), dev(sc.fuel0)
+    t2, f2 = dev(sc.T0), dev(sc.fuel0)
+    for _ in range(37):
+        pl.step(t1, f1)
+    pl.run(t2, f2, 37)        # 2 graph replays of 16 + 5 eager steps
+    assert torch.equal(t1, t2) and torch.equal(f1, f2)
+    t3, f3 = dev(sc.T0), dev(sc.fuel0)
+    pl.run(t3, f3, 37)
+    assert torch.equal(t3, t2) and torch.equal(f3, f2)
+
+
+def test_invalid_calls_on_device():
+    sc = inputs.small_case(1, 20, 20, 2, "strang")
+    pl = iga.Plan.from_scenario(sc)
+    t, f = dev(sc.T0), dev(sc.fuel0)
+    with pytest.raises(iga.IgaError) as e:
+        pl.step(t, f)             # not factored yet
+    assert e.value.status == iga.ESTATE
+    pl.factor()
+    r = torch.zeros_like(t)
+    with pytest.raises(iga.IgaError) as e:
+        pl.assemble_rhs(1, t, f, r)   # Strang middle substep has no quadrature RHS
+    assert e.value.status == iga.EINVAL
+    with pytest.raises(iga.IgaError) as e:
+        pl.assemble_rhs(0, t, f, t)   # aliasing
+    assert e.value.status == iga.EINVAL
+    with pytest.raises(iga.IgaError) as e:
+        pl.step(t, t)
+    assert e.value.status == iga.EINVAL
+
+
+def test_nonfinite_detection():
+    sc = inputs.small_case(2, 24, 24, 2, "pr")
+    pl = iga.Plan.from_scenario(sc, check_every=2)
+    pl.factor()
+    T = sc.T0.copy()
+    T[5, 7] = np.nan
+    t, f = dev(T), dev(sc.fuel0)
+    with pytest.raises(iga.IgaError) as e:
+        pl.run(t, f, 4)
+    assert e.value.status == iga.ENONFINITE
+    t2, f2 = dev(sc.T0), dev(sc.fuel0)
+    pl.run(t2, f2, 4)
+    assert torch.isfinite(t2).all()
