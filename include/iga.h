@@ -135,7 +135,10 @@ iga_status iga_factor_1d(iga_plan *plan, void *stream);
  * fuel v.  All four are fields (layout above); rhs buffers must not alias the
  * inputs.  The Strang middle substep has no quadrature right-hand side (it is
  * iga_line_solve(dir = 1, which = 2)): substep 1 of a Strang plan is
- * IGA_EINVAL. */
+ * IGA_EINVAL.
+ * IGA_FP32_REFINE plans return the increment form R - (A^x (x) M^y) T
+ * (PR substep 1: R - (M^x (x) A^y) T; fuel: R_fuel - (M^x (x) M^y) fuel), whose
+ * solve is the change of the state over the substep. */
 iga_status iga_assemble_rhs(const iga_plan *plan, int32_t substep, const void *T,
                             const void *fuel, void *rhs_T, void *rhs_fuel, void *stream);
 
@@ -165,17 +168,16 @@ iga_status iga_step(iga_plan *plan, void *T, void *fuel, void *stream);
  * IGA_ENONFINITE is returned at the first failure (state left as computed). */
 iga_status iga_run(iga_plan *plan, void *T, void *fuel, int64_t nsteps, void *stream);
 
-/* Line-solve schedule chosen for direction dir: lines per wavefront `lw`,
- * rows per lane `m`, chunks per line `chunks`, waves per workgroup `waves`. */
-iga_status iga_plan_schedule(const iga_plan *plan, int32_t dir, int32_t *lw, int32_t *m,
-                             int32_t *chunks, int32_t *waves);
+/* Line-solve schedule of direction dir: wavefronts (= lines) per workgroup,
+ * rows per lane m (each line is split into 64 chunks of m rows) and the
+ * compiled register capacity used for m. */
+iga_status iga_plan_schedule(const iga_plan *plan, int32_t dir, int32_t *waves, int32_t *m,
+                             int32_t *capacity);
 
-/* Choose a different line-solve schedule for direction dir (autotuning).
- * lw in {64, 16, 8}; waves in {4, 8, 16}; the rows per lane follow from the
- * line length.  Re-derives the chunk tables on `stream` if already factored.
- * IGA_EUNSUPPORTED if the combination is not compiled or does not fit. */
-iga_status iga_plan_set_schedule(iga_plan *plan, int32_t dir, int32_t lw, int32_t waves,
-                                 void *stream);
+/* Choose the number of lines per workgroup for direction dir (autotuning):
+ * waves in {1, 2, 4, 8, 16}.  IGA_EUNSUPPORTED if the workgroup does not fit
+ * the register or LDS budget for this line length. */
+iga_status iga_plan_set_schedule(iga_plan *plan, int32_t dir, int32_t waves);
 
 /* Assembly schedule: element rows marched per wavefront (>= 1). */
 iga_status iga_plan_set_assembly_rows(iga_plan *plan, int32_t rows);

@@ -67,33 +67,39 @@ static iga_status check_field(const void *p, const char *name)
 }
 
 // One step in place; the right-hand sides live in the plan's scratch buffers.
+// FP32 plans advance in increment form: the assembled right-hand sides are
+// R - (implicit operator) S, the solves give the increment, and the y sweep
+// adds the state it was taken from.
 static iga_status step_impl(iga_plan *pl, void *T, void *fuel, hipStream_t s)
 {
     void *R = pl->scratch_r.ptr, *RF = pl->scratch_rf.ptr;
+    const void *bT = pl->delta ? T : nullptr, *bF = pl->delta ? fuel : nullptr;
+    const int add = pl->delta ? 1 : 0;
     iga_status st;
     const bool pr = pl->d.scheme == IGA_PR;
     // substep 1 (PR: x implicit; Strang: S1) + the fuel right-hand side
     if ((st = launch_assemble(pl, 0, T, fuel, R, RF, s))) return st;
-    SweepJob jx[2] = {{R, R, OP_AX, -1, -1}, {RF, RF, OP_MX, -1, -1}};
+    SweepJob jx[2] = {{R, R, OP_AX, -1, -1, nullptr, 0}, {RF, RF, OP_MX, -1, -1, nullptr, 0}};
     if ((st = launch_sweep(pl, 0, jx, 2, s))) return st;
     if (pr) {
-        SweepJob jy[1] = {{R, T, OP_MY, -1, -1}};
+        SweepJob jy[1] = {{R, T, OP_MY, -1, -1, bT, 0}};
         if ((st = launch_sweep(pl, 1, jy, 1, s))) return st;
         // substep 2: y implicit
         if ((st = launch_assemble(pl, 1, T, fuel, R, nullptr, s))) return st;
-        SweepJob jx2[1] = {{R, R, OP_MX, -1, -1}};
+        SweepJob jx2[1] = {{R, R, OP_MX, -1, -1, nullptr, 0}};
         if ((st = launch_sweep(pl, 0, jx2, 1, s))) return st;
-        SweepJob jy2[2] = {{R, T, OP_AY, -1, -1}, {RF, fuel, OP_MY, -1, -1}};
+        SweepJob jy2[2] = {{R, T, OP_AY, -1, -1, bT, 0}, {RF, fuel, OP_MY, -1, -1, bF, 0}};
         if ((st = launch_sweep(pl, 1, jy2, 2, s))) return st;
     } else {
-        // S1's y solve fused with S2: T** = (A^y)^{-1} B^y (M^y)^{-1} R along y
-        SweepJob jy[1] = {{R, T, OP_MY, BAND_BY, OP_AY}};
+        // S1's y solve fused with S2: T** = (A^y)^{-1} B^y T* along y, with
+        // T* = (M^y)^{-1} R (+ T^n in increment form)
+        SweepJob jy[1] = {{R, T, OP_MY, BAND_BY, OP_AY, bT, add}};
         if ((st = launch_sweep(pl, 1, jy, 1, s))) return st;
         // S3
         if ((st = launch_assemble(pl, 2, T, fuel, R, nullptr, s))) return st;
-        SweepJob jx2[1] = {{R, R, OP_AX, -1, -1}};
+        SweepJob jx2[1] = {{R, R, OP_AX, -1, -1, nullptr, 0}};
         if ((st = launch_sweep(pl, 0, jx2, 1, s))) return st;
-        SweepJob jy2[2] = {{R, T, OP_MY, -1, -1}, {RF, fuel, OP_MY, -1, -1}};
+        SweepJob jy2[2] = {{R, T, OP_MY, -1, -1, bT, 0}, {RF, fuel, OP_MY, -1, -1, bF, 0}};
         if ((st = launch_sweep(pl, 1, jy2, 2, s))) return st;
     }
     return IGA_OK;
@@ -178,11 +184,11 @@ iga_status iga_plan_create(const iga_plan_desc *desc, iga_plan **out)
     try {
         pl->d = *desc;
         if ((st = build_plan_host(pl)) || (st = upload_plan(pl)) ||
-            (st = choose_schedule(pl, 0, 0, 0)) || (st = choose_schedule(pl, 1, 0, 0))) {
+            (st = choose_schedule(pl, 0, 0)) || (st = choose_schedule(pl, 1, 0))) {
             delete pl;
             return st;
         }
-        pl->asm_rows = pl->Nx >= 2048 ? 64 : (pl->Nx >= 512 ? 32 : 16);
+        pl->asm_rows = pl->Nx >= 2048 ? 32 : 16;
     } catch (const std::bad_alloc &) {
         delete pl;
         return fail(IGA_ENOMEM, "host allocation failed");
@@ -214,6 +220,10 @@ iga_status iga_factor_1d(iga_plan *plan, void *stream)
     if (!plan) return fail(IGA_EINVAL, "plan is NULL");
     iga_status st = launch_factor(plan, static_cast<hipStream_t>(stream));
     if (st) return st;
+    // the tables are known now: make sure each schedule still fits LDS
+    for (int dir = 0; dir < 2; ++dir)
+        if (sweep_lds_bytes(plan, dir, plan->sched[dir].waves) > 160 * 1024)
+            if ((st = choose_schedule(plan, dir, 0))) return st;
     plan->factored = true;
     plan->graph.reset();
     return IGA_OK;
@@ -247,13 +257,11 @@ iga_status iga_line_solve(const iga_plan *plan, int32_t dir, int32_t which, void
     iga_status st = check_field(x, "x");
     if (st) return st;
     if (!plan->factored) return fail(IGA_ESTATE, "iga_factor_1d has not been called");
-    SweepJob j;
-    j.src = x;
-    j.dst = x;
     const int A = dir ? OP_AY : OP_AX, M = dir ? OP_MY : OP_MX;
-    if (which == 0) j = {x, x, A, -1, -1};
-    else if (which == 1) j = {x, x, M, -1, -1};
-    else j = {x, x, -1, dir ? BAND_BY : BAND_BX, A};
+    const int B = dir ? BAND_BY : BAND_BX;
+    SweepJob j{x, x, A, -1, -1, nullptr, 0};
+    if (which == 1) j.op0 = M;
+    if (which == 2) j = SweepJob{x, x, -1, B, A, nullptr, plan->delta ? 1 : 0};
     return launch_sweep(plan, dir, &j, 1, static_cast<hipStream_t>(stream));
 }
 
@@ -301,40 +309,31 @@ iga_status iga_run(iga_plan *plan, void *T, void *fuel, int64_t nsteps, void *st
     return IGA_OK;
 }
 
-iga_status iga_plan_schedule(const iga_plan *plan, int32_t dir, int32_t *lw, int32_t *m,
-                             int32_t *chunks, int32_t *waves)
+iga_status iga_plan_schedule(const iga_plan *plan, int32_t dir, int32_t *waves, int32_t *m,
+                             int32_t *capacity)
 {
     if (!plan) return fail(IGA_EINVAL, "plan is NULL");
     if (dir != 0 && dir != 1) return fail(IGA_EINVAL, "dir must be 0 or 1");
     const Schedule &sc = plan->sched[dir];
-    if (lw) *lw = sc.lw;
-    if (m) *m = sc.m;
-    if (chunks) *chunks = sc.chunks;
     if (waves) *waves = sc.waves;
+    if (m) *m = sc.m;
+    if (capacity) *capacity = sc.mm;
     return IGA_OK;
 }
 
-iga_status iga_plan_set_schedule(iga_plan *plan, int32_t dir, int32_t lw, int32_t waves, void *stream)
+iga_status iga_plan_set_schedule(iga_plan *plan, int32_t dir, int32_t waves)
 {
     if (!plan) return fail(IGA_EINVAL, "plan is NULL");
     if (dir != 0 && dir != 1) return fail(IGA_EINVAL, "dir must be 0 or 1");
-    if (lw != 64 && lw != 16 && lw != 8) return fail(IGA_EINVAL, "lw must be 64, 16 or 8");
-    if (waves != 4 && waves != 8 && waves != 16) return fail(IGA_EINVAL, "waves must be 4, 8 or 16");
+    if (waves != 1 && waves != 2 && waves != 4 && waves != 8 && waves != 16)
+        return fail(IGA_EINVAL, "waves must be 1, 2, 4, 8 or 16");
     Schedule old = plan->sched[dir];
-    iga_status st = choose_schedule(plan, dir, lw, waves);
+    iga_status st = choose_schedule(plan, dir, waves);
     if (st) {
         plan->sched[dir] = old;
         return st;
     }
     plan->graph.reset();
-    if (plan->factored) {
-        hipStream_t s = static_cast<hipStream_t>(stream);
-        for (int op = 0; op < NOPS; ++op) {
-            if (((op == OP_AX || op == OP_MX) ? 0 : 1) != dir) continue;
-            if ((st = launch_chunk_tables(plan, op, s))) return st;
-        }
-        IGA_HIP(hipStreamSynchronize(s));
-    }
     return IGA_OK;
 }
 

@@ -10,6 +10,9 @@
 //       + [S > T_ig and fuel > thr] C_ign S exp(-T_act/S)
 // and, for the first substep of a step, the fuel right-hand side of the
 // compute_rhs listing (Section 7): fuel v (1 - tau rate [ign] S exp(-T_act/S)).
+// FP32 plans assemble the same quantities in increment form, R - A_impl S
+// (A_impl the substep's implicit Kronecker operator), so that the float
+// right-hand side carries only the O(tau) change of the state.
 //
 // Schedule: one wavefront owns a strip of 64 element columns (lane = element
 // column ey, the strip's first p lanes are halo) and marches along x over a
@@ -32,8 +35,11 @@ template <typename T> struct AsmParams {
     const T *bx, *by;   // [e][2][Q][Q]: (values, derivatives)[a][q]
     const T *wx, *wy;   // (b_y(x) - bbar_y) at x-points, (b_x(y) - bbar_x) at y-points
     T w[16];            // w_qx w_qy |J| per point (uniform mesh)
-    T alpha, beta, c_adv, c_diff, react_e, bbar_e, c_nld, c_ign, t_ig, fthr, t_act, c_forc,
-        c_rad, fuel_dt_rate;
+    // integrand  a0 v + ax v_x + ay v_y  with
+    //   a0 = cs S - cx S_x - cy S_y + beta f,  ax = -(dx + beta g) S_x,  ay = -(dy + beta g) S_y
+    T cs, cx, cy, dx, dy, beta;
+    T c_adv, c_nld, c_ign, t_ig, fthr, t_act, c_forc, c_rad;
+    T cf, fuel_dt_rate;   // fuel: a0f = F (cf - tau rate arr)
     int nel_x, nel_y, Nx, Ny, rows, nstrips, ntiles;
 };
 
@@ -47,7 +53,7 @@ template <typename T> __device__ __forceinline__ T arrhenius(T S, T t_act)
     return S * exp(-t_act / S);
 }
 
-template <typename T, int P, bool FUEL, int EDIR>
+template <typename T, int P, bool FUEL>
 __global__ __launch_bounds__(256) void k_assemble(AsmParams<T> a)
 {
     constexpr int Q = P + 1;
@@ -59,6 +65,8 @@ __global__ __launch_bounds__(256) void k_assemble(AsmParams<T> a)
     const int ey = J0 - P + lane;
     const bool eyok = ey >= 0 && ey < a.nel_y;
     const int Ny = a.Ny;
+    const int colA = J0 - P + lane, colB = colA + 64;
+    const bool okA = colA >= 0 && colA < Ny, okB = lane < P && colB < Ny;
 
     T byv[Q][Q], byd[Q][Q], wyr[Q];
 #pragma unroll
@@ -71,21 +79,23 @@ __global__ __launch_bounds__(256) void k_assemble(AsmParams<T> a)
 #pragma unroll
     for (int q = 0; q < Q; ++q) wyr[q] = eyok ? a.wy[(size_t)ey * Q + q] : T(0);
 
-    // y half of the sum factorisation for coefficient row `row`
-    auto load_row = [&](int row, T(&v)[Q], T(&d)[Q], T(&f)[Q]) {
-        T c0 = 0, c1 = 0, f0 = 0, f1 = 0;
+    // raw coefficients of row `row` for columns colA (and colB for the halo)
+    auto fetch = [&](int row, T &c0, T &c1, T &f0, T &f1) {
+        c0 = c1 = f0 = f1 = T(0);
         if (row >= 0 && row < a.Nx) {
-            const int colA = J0 - P + lane, colB = colA + 64;
             const size_t base = (size_t)row * Ny;
-            if (colA >= 0 && colA < Ny) {
+            if (okA) {
                 c0 = a.S[base + colA];
                 f0 = a.F[base + colA];
             }
-            if (lane < P && colB < Ny) {
+            if (okB) {
                 c1 = a.S[base + colB];
                 f1 = a.F[base + colB];
             }
         }
+    };
+    // y half of the sum factorisation of one fetched row
+    auto ytransform = [&](T c0, T c1, T f0, T f1, T(&v)[Q], T(&d)[Q], T(&f)[Q]) {
         T cb[Q], fb[Q];
         cb[0] = c0;
         fb[0] = f0;
@@ -121,10 +131,18 @@ __global__ __launch_bounds__(256) void k_assemble(AsmParams<T> a)
 #pragma unroll
         for (int q = 0; q < Q; ++q) acc0[i][q] = acc1[i][q] = accf[i][q] = T(0);
 #pragma unroll
-    for (int s = 0; s < P; ++s) load_row(X0 - P + s, tv[s], td[s], tf[s]);
+    for (int s = 0; s < P; ++s) {
+        T c0, c1, f0, f1;
+        fetch(X0 - P + s, c0, c1, f0, f1);
+        ytransform(c0, c1, f0, f1, tv[s], td[s], tf[s]);
+    }
+    T nc0, nc1, nf0, nf1;   // row ex + P, fetched one iteration ahead
+    fetch(X0, nc0, nc1, nf0, nf1);
 
     for (int ex = X0 - P; ex < X1; ++ex) {
-        load_row(ex + P, tv[P], td[P], tf[P]);
+        const T c0 = nc0, c1 = nc1, f0 = nf0, f1 = nf1;
+        fetch(ex + P + 1, nc0, nc1, nf0, nf1);
+        ytransform(c0, c1, f0, f1, tv[P], td[P], tf[P]);
         if (ex >= 0 && ex < a.nel_x) {
             const T *bxe = a.bx + (size_t)ex * 2 * Q * Q;
             T bxv[Q][Q], bxd[Q][Q], wxr[Q];
@@ -156,17 +174,17 @@ __global__ __launch_bounds__(256) void k_assemble(AsmParams<T> a)
                     T arr = T(0);
                     if (S > a.t_ig && F > a.fthr) arr = arrhenius(S, a.t_act);
                     f += a.c_ign * arr;
-                    const T dSe = EDIR ? Sy : Sx;
-                    const T a0 = W * (S + a.alpha * (a.react_e * S - a.c_adv * a.bbar_e * dSe) + a.beta * f);
-                    const T ax = W * ((EDIR ? T(0) : -a.alpha * a.c_diff) - a.beta * g) * Sx;
-                    const T ay = W * ((EDIR ? -a.alpha * a.c_diff : T(0)) - a.beta * g) * Sy;
+                    const T a0 = W * (a.cs * S - a.cx * Sx - a.cy * Sy + a.beta * f);
+                    const T bg = a.beta * g;
+                    const T ax = -W * (a.dx + bg) * Sx;
+                    const T ay = -W * (a.dy + bg) * Sy;
 #pragma unroll
                     for (int i = 0; i < Q; ++i) {
                         acc0[i][qy] += a0 * bxv[i][qx] + ax * bxd[i][qx];
                         acc1[i][qy] += ay * bxv[i][qx];
                     }
                     if (FUEL) {
-                        const T af = W * F * (T(1) - a.fuel_dt_rate * arr);
+                        const T af = W * F * (a.cf - a.fuel_dt_rate * arr);
 #pragma unroll
                         for (int i = 0; i < Q; ++i) accf[i][qy] += af * bxv[i][qx];
                     }
@@ -193,10 +211,9 @@ __global__ __launch_bounds__(256) void k_assemble(AsmParams<T> a)
                 r += shfl(pb[b], (lane - b) & 63);
                 if (FUEL) rf += shfl(pf[b], (lane - b) & 63);
             }
-            const int col = J0 - P + lane;
-            if (lane >= P && col < Ny) {
-                a.R[(size_t)ex * Ny + col] = r;
-                if (FUEL) a.RF[(size_t)ex * Ny + col] = rf;
+            if (lane >= P && colA < Ny) {
+                a.R[(size_t)ex * Ny + colA] = r;
+                if (FUEL) a.RF[(size_t)ex * Ny + colA] = rf;
             }
         }
         // roll the windows
@@ -234,22 +251,41 @@ static iga_status launch_t(const iga_plan *pl, int substep, const void *S, const
     a.wy = pl->asm_wy.as<T>();
     for (int qx = 0; qx < Q; ++qx)
         for (int qy = 0; qy < Q; ++qy) a.w[qx * Q + qy] = (T)(pl->X.wq[qx] * pl->Y.wq[qy]);
-    int edir;
-    double alpha, beta;
+    // weights of the explicit (kx_e, ky_e) and implicit (kx_i, ky_i) parts of
+    // the linear operator in this substep, and of F (beta)
+    double kx_e = 0, ky_e = 0, kx_i = 0, ky_i = 0, beta;
     if (d.scheme == IGA_PR) {
-        edir = substep == 0 ? 1 : 0;
-        alpha = beta = 0.5 * d.dt;
+        // substep 0: x implicit, L2 (y) explicit; substep 1: y implicit, L1 (x) explicit
+        const double h = 0.5 * d.dt;
+        if (substep == 0) { ky_e = h; kx_i = h; }
+        else { kx_e = h; ky_i = h; }
+        beta = h;
     } else {
-        edir = 0;
-        alpha = 0.25 * d.dt;
+        // S1 / S3: Crank-Nicolson on L1 over tau/2 (explicit and implicit halves)
+        kx_e = kx_i = 0.25 * d.dt;
         beta = 0.5 * d.dt;
     }
-    a.alpha = (T)alpha;
+    const double react = d.c.c_react;
+    double cs, kx, ky;
+    if (pl->delta) {
+        // increment form: R - (implicit operator) S
+        kx = kx_e + kx_i;
+        ky = ky_e + ky_i;
+        cs = kx * react;
+        a.cf = T(0);
+    } else {
+        kx = kx_e;
+        ky = ky_e;
+        cs = 1.0 + kx * react;
+        a.cf = T(1);
+    }
+    a.cs = (T)cs;
+    a.cx = (T)(kx * d.c.c_adv * d.wind.bbar_x);
+    a.cy = (T)(ky * d.c.c_adv * d.wind.bbar_y);
+    a.dx = (T)(kx * d.c.c_diff);
+    a.dy = (T)(ky * d.c.c_diff);
     a.beta = (T)beta;
     a.c_adv = (T)d.c.c_adv;
-    a.c_diff = (T)d.c.c_diff;
-    a.react_e = (T)(edir ? 0.0 : d.c.c_react);
-    a.bbar_e = (T)(edir ? d.wind.bbar_y : d.wind.bbar_x);
     a.c_nld = (T)d.c.c_nld;
     a.c_ign = (T)d.c.c_ign;
     a.t_ig = (T)d.c.t_ig;
@@ -268,14 +304,14 @@ static iga_status launch_t(const iga_plan *pl, int substep, const void *S, const
     const int waves = a.nstrips * a.ntiles;
     const int blocks = (waves + 3) / 4;
     const bool fuel = RF != nullptr;
-#define IGA_ASM(P_, FU_, E_)                                                                   \
-    hipLaunchKernelGGL((k_assemble<T, P_, FU_, E_>), dim3(blocks), dim3(256), 0, s, a)
+#define IGA_ASM(P_, FU_) \
+    hipLaunchKernelGGL((k_assemble<T, P_, FU_>), dim3(blocks), dim3(256), 0, s, a)
     if (P == 2) {
-        if (fuel) { if (edir) IGA_ASM(2, true, 1); else IGA_ASM(2, true, 0); }
-        else { if (edir) IGA_ASM(2, false, 1); else IGA_ASM(2, false, 0); }
+        if (fuel) IGA_ASM(2, true);
+        else IGA_ASM(2, false);
     } else if (P == 3) {
-        if (fuel) { if (edir) IGA_ASM(3, true, 1); else IGA_ASM(3, true, 0); }
-        else { if (edir) IGA_ASM(3, false, 1); else IGA_ASM(3, false, 0); }
+        if (fuel) IGA_ASM(3, true);
+        else IGA_ASM(3, false);
     } else {
         return fail(IGA_EUNSUPPORTED, "degree not compiled");
     }

@@ -6,8 +6,8 @@
 
 #include <algorithm>
 #include <cstddef>
-#include <cstring>
 #include <cstdint>
+#include <cstring>
 #include <string>
 #include <vector>
 
@@ -56,23 +56,30 @@ struct DevBuf {
 enum OpId { OP_AX = 0, OP_MX = 1, OP_AY = 2, OP_MY = 3, NOPS = 4 };
 enum BandId { BAND_BX = 0, BAND_BY = 1, NBANDS = 2 };
 
-// Schedule of the chunked line solve in one direction: a workgroup of `waves`
-// wavefronts owns `lw` whole lines; lane (line l, chunk c) holds rows
-// [c*m, c*m + m) of line l in registers (mm = compiled register capacity).
+inline int op_dir(int op) { return (op == OP_AX || op == OP_MX) ? 0 : 1; }
+
+// Schedule of the line solves in one direction: a workgroup of `waves`
+// wavefronts owns `waves` lines, one per wavefront; each lane holds a chunk of
+// m consecutive rows (64 chunks per line) in a register array of capacity mm.
 struct Schedule {
-    int lw = 16, waves = 16, mm = 32, m = 0, chunks = 0, levels = 0;
+    int waves = 4, mm = 17, m = 0;
 };
 
-// Device pointers of one factored operator (all arrays indexed by row r of
-// the line, length N):
-//   lf[r*P + j]      multiplier L(r, r-1-j) of the unit lower factor
-//   uf[r*(P+1)]      1 / U(r, r);  uf[r*(P+1) + 1 + j] = U(r, r+1+j) / U(r, r)
-//   tf[(d*C + c)*P*P] forward transfer of chunks c-2^d+1 .. c (scan level d)
-//   tb[(d*C + c)*P*P] backward transfer of chunks c .. c+2^d-1
-//   a64[r*(2P+1) + (k - r + P)]  the operator itself in double
-struct OpDev {
-    const void *lf, *uf, *tf, *tb;
-    const double *a64;
+// Compressed coefficient tables of one banded operator (host copy).  Rows
+// [0, K0) and [NK, N) are kept, the interior rows [K0, NK) -- equal to
+// rounding on a uniform mesh -- share the canonical row K0.
+//   rows[i*RS + j]      j < P: L(r, r-1-j);  rows[i*RS + P] = 1/U(r,r);
+//                       rows[i*RS + P + 1 + j] = U(r, r+1+j)/U(r,r)
+//   a64[i*RS + j]       A(r, r-P+j), j <= 2P (the operator, for refinement)
+//   tf[(d*64 + c)*P*P]  forward transfer of chunks c-2^d+1 .. c
+//   tb[(d*64 + c)*P*P]  backward transfer of chunks c .. c+2^d-1
+struct OpHost {
+    int K0 = 0, NK = 0, nrows = 0;
+    std::vector<double> rows, a64, tf, tb;
+};
+struct BandHost {
+    int K0 = 0, NK = 0, nrows = 0;
+    std::vector<double> rows;   // band row r-P .. r+P
 };
 
 struct DirHost {
@@ -111,18 +118,22 @@ struct iga_plan {
     int P = 2, Nx = 0, Ny = 0;
     size_t ndof = 0;
     bool fp32 = false;
+    bool delta = false;           // increment form (FP32 plans)
     size_t wsize = 8;             // bytes per state element
     iga::DirHost X, Y;
     std::vector<double> op_band[iga::NOPS];    // host FP64 operators
-    std::vector<double> cn_band[iga::NBANDS];  // explicit CN counterparts
+    std::vector<double> cn_band[iga::NBANDS];  // explicit CN operators (B, or B - A)
     iga::Schedule sched[2];
-    int asm_rows = 32;
+    int asm_rows = 16;
 
-    // device tables
+    // device LU (input bands and factors, double)
     iga::DevBuf op_a64[iga::NOPS], op_lf64[iga::NOPS], op_uf64[iga::NOPS];
-    iga::DevBuf op_tf64[iga::NOPS], op_tb64[iga::NOPS];
-    iga::DevBuf op_lf32[iga::NOPS], op_uf32[iga::NOPS], op_tf32[iga::NOPS], op_tb32[iga::NOPS];
-    iga::DevBuf cn_dev[iga::NBANDS];           // explicit bands, state precision
+    // compressed tables used by the line solves
+    iga::OpHost op_host[iga::NOPS];
+    iga::BandHost band_host[iga::NBANDS];
+    iga::DevBuf op_rows[iga::NOPS], op_a64c[iga::NOPS], op_tf[iga::NOPS], op_tb[iga::NOPS];
+    iga::DevBuf band_rows[iga::NBANDS];
+    // assembly tables
     iga::DevBuf asm_bx, asm_by;                // [e][2][P+1][P+1]  (val, der), state precision
     iga::DevBuf asm_wx, asm_wy;                // wind remainders at x-qps / y-qps
     iga::DevBuf scratch_r, scratch_rf;         // right-hand sides
@@ -136,12 +147,11 @@ namespace iga {
 // host side (plan.cpp)
 iga_status build_plan_host(iga_plan *pl);
 iga_status upload_plan(iga_plan *pl);
-iga_status choose_schedule(iga_plan *pl, int dir, int lw, int waves);
-OpDev op_dev(const iga_plan *pl, int op);
+iga_status choose_schedule(iga_plan *pl, int dir, int waves);
+iga_status build_solve_tables(iga_plan *pl);
 
 // kernels (factor.hip)
 iga_status launch_factor(iga_plan *pl, hipStream_t s);
-iga_status launch_chunk_tables(iga_plan *pl, int op, hipStream_t s);
 
 // kernels (assemble.hip)
 iga_status launch_assemble(const iga_plan *pl, int substep, const void *T, const void *fuel,
@@ -151,15 +161,17 @@ iga_status launch_assemble(const iga_plan *pl, int substep, const void *T, const
 struct SweepJob {
     const void *src;
     void *dst;
-    int op0;    // first solve
-    int band;   // explicit band applied after the first solve (-1: none)
-    int op1;    // second solve (-1: none)
+    int op0;          // first solve (-1: none)
+    int band;         // explicit band applied after the first solve (-1: none)
+    int op1;          // solve applied to the band product (-1: none)
+    const void *base; // added after the first solve (increment form), or NULL
+    int add_after;    // 1: result = x + op1^{-1} band x; 0: result = op1^{-1} band x
 };
 iga_status launch_sweep(const iga_plan *pl, int dir, const SweepJob *jobs, int njobs,
                         hipStream_t s);
-bool sweep_compiled(int P, int lw, int mm);
+int sweep_capacity(int m);           // smallest compiled register capacity >= m (0: none)
 iga_status sweep_prepare(const iga_plan *pl, int dir);
-size_t sweep_lds_bytes(const iga_plan *pl, int dir, const Schedule &sc);
+size_t sweep_lds_bytes(const iga_plan *pl, int dir, int waves);
 
 // kernels (util)
 iga_status launch_nonfinite(const iga_plan *pl, const void *T, const void *fuel, int *flag,

@@ -92,13 +92,19 @@ static void build_dir(DirHost &D, int n, int p, double L)
     D.M.assign((size_t)D.N * W, 0.0);
     D.K.assign((size_t)D.N * W, 0.0);
     D.G.assign((size_t)D.N * W, 0.0);
+    // Basis functions are evaluated in element-local coordinates: on a uniform
+    // knot vector the knots seen from element e are exact multiples of h, so
+    // every interior element gets bitwise the same tables (and the interior
+    // rows of M, K, G are exactly Toeplitz) with no cancellation at large x.
+    std::vector<double> tl(n + 2 * p + 1);
     for (int e = 0; e < n; ++e) {
-        double a = D.knots[p + e], b = D.knots[p + e + 1];
+        for (int k = 0; k < n + 2 * p + 1; ++k)
+            tl[k] = (double)(std::min(std::max(k - p, 0), n) - e) * D.h;
         for (int q = 0; q < nq; ++q) {
-            double x = a + 0.5 * (gx[q] + 1.0) * (b - a);
-            D.xq[(size_t)e * nq + q] = x;
+            const double xl = 0.5 * (gx[q] + 1.0) * D.h;
+            D.xq[(size_t)e * nq + q] = D.knots[p + e] + xl;
             double v[4], dv[4];
-            basis_ders(D.knots, p + e, p, x, v, dv);
+            basis_ders(tl, p + e, p, xl, v, dv);
             for (int r = 0; r <= p; ++r) {
                 D.bv[((size_t)e * nq + r) * nq + q] = v[r];
                 D.bd[((size_t)e * nq + r) * nq + q] = dv[r];
@@ -135,6 +141,7 @@ iga_status build_plan_host(iga_plan *pl)
     pl->Ny = pl->Y.N;
     pl->ndof = (size_t)pl->Nx * pl->Ny;
     pl->fp32 = d.precision == IGA_FP32_REFINE;
+    pl->delta = pl->fp32;
     pl->wsize = pl->fp32 ? 4 : 8;
     for (int dir = 0; dir < 2; ++dir) {
         const DirHost &D = dir ? pl->Y : pl->X;
@@ -146,7 +153,10 @@ iga_status build_plan_host(iga_plan *pl)
         for (size_t k = 0; k < n; ++k) {
             double lin = d.c.c_diff * D.K[k] + d.c.c_adv * bbar * D.G[k];
             A[k] = (1.0 - g * react) * D.M[k] + g * lin;
-            B[k] = (1.0 + g * react) * D.M[k] - g * lin;
+            // explicit Crank-Nicolson counterpart B = (1 + g react) M - g (...);
+            // in increment form the line solve applies B - A = 2 g (react M - (...))
+            B[k] = pl->delta ? 2.0 * g * (react * D.M[k] - lin)
+                             : (1.0 + g * react) * D.M[k] - g * lin;
         }
         pl->op_band[dir ? OP_AY : OP_AX] = A;
         pl->op_band[dir ? OP_MY : OP_MX] = M;
@@ -173,6 +183,11 @@ template <typename T> static iga_status upload_vec(DevBuf &b, const std::vector<
     return upload(b, c.data(), c.size() * sizeof(T));
 }
 
+static iga_status upload_state(const iga_plan *pl, DevBuf &b, const std::vector<double> &v)
+{
+    return pl->fp32 ? upload_vec<float>(b, v) : upload_vec<double>(b, v);
+}
+
 // Assembly tables of one direction: per element e, [0][a][q] values and
 // [1][a][q] derivatives of the element's p+1 functions at its p+1 points.
 static std::vector<double> asm_table(const DirHost &D, int p)
@@ -193,14 +208,8 @@ iga_status upload_plan(iga_plan *pl)
     const int p = pl->P, nq = p + 1;
     const iga_plan_desc &d = pl->d;
     iga_status st;
-    for (int op = 0; op < NOPS; ++op) {
+    for (int op = 0; op < NOPS; ++op)
         if ((st = upload_vec<double>(pl->op_a64[op], pl->op_band[op]))) return st;
-    }
-    for (int b = 0; b < NBANDS; ++b) {
-        st = pl->fp32 ? upload_vec<float>(pl->cn_dev[b], pl->cn_band[b])
-                      : upload_vec<double>(pl->cn_dev[b], pl->cn_band[b]);
-        if (st) return st;
-    }
     std::vector<double> tx = asm_table(pl->X, p), ty = asm_table(pl->Y, p);
     // explicit wind remainders: (by(x) - bbar_y) at x-points, (bx(y) - bbar_x) at y-points
     std::vector<double> wx((size_t)pl->X.n * nq), wy((size_t)pl->Y.n * nq);
@@ -217,33 +226,173 @@ iga_status upload_plan(iga_plan *pl)
             double bx = d.wind.bx + (sc ? d.wind.ax * std::sin(2.0 * M_PI * y / d.len_y) : 0.0);
             wy[(size_t)e * nq + q] = bx - d.wind.bbar_x;
         }
-    if (pl->fp32) {
-        if ((st = upload_vec<float>(pl->asm_bx, tx))) return st;
-        if ((st = upload_vec<float>(pl->asm_by, ty))) return st;
-        if ((st = upload_vec<float>(pl->asm_wx, wx))) return st;
-        if ((st = upload_vec<float>(pl->asm_wy, wy))) return st;
-    } else {
-        if ((st = upload_vec<double>(pl->asm_bx, tx))) return st;
-        if ((st = upload_vec<double>(pl->asm_by, ty))) return st;
-        if ((st = upload_vec<double>(pl->asm_wx, wx))) return st;
-        if ((st = upload_vec<double>(pl->asm_wy, wy))) return st;
-    }
+    if ((st = upload_state(pl, pl->asm_bx, tx))) return st;
+    if ((st = upload_state(pl, pl->asm_by, ty))) return st;
+    if ((st = upload_state(pl, pl->asm_wx, wx))) return st;
+    if ((st = upload_state(pl, pl->asm_wy, wy))) return st;
     IGA_HIP(pl->scratch_r.alloc(pl->ndof * pl->wsize));
     IGA_HIP(pl->scratch_rf.alloc(pl->ndof * pl->wsize));
     IGA_HIP(pl->flag.alloc(64));
-    for (int dir = 0; dir < 2; ++dir) {
-        int N = dir ? pl->Ny : pl->Nx;
-        int lines = dir ? pl->Nx : pl->Ny;
-        (void)lines;
-        for (int op = 0; op < NOPS; ++op) {
-            if ((op == OP_AX || op == OP_MX) != (dir == 0)) continue;
-            IGA_HIP(pl->op_lf64[op].alloc((size_t)N * p * 8));
-            IGA_HIP(pl->op_uf64[op].alloc((size_t)N * (p + 1) * 8));
-            if (pl->fp32) {
-                IGA_HIP(pl->op_lf32[op].alloc((size_t)N * p * 4));
-                IGA_HIP(pl->op_uf32[op].alloc((size_t)N * (p + 1) * 4));
-            }
+    for (int op = 0; op < NOPS; ++op) {
+        const int N = op_dir(op) ? pl->Ny : pl->Nx;
+        IGA_HIP(pl->op_lf64[op].alloc((size_t)N * p * 8));
+        IGA_HIP(pl->op_uf64[op].alloc((size_t)N * (p + 1) * 8));
+    }
+    return IGA_OK;
+}
+
+// ---------------------------------------------------------------------------
+// line-solve tables: compressed coefficient rows and chunk scan tables
+// ---------------------------------------------------------------------------
+// Rows of `f` (stride RS, N rows) that agree with the middle row to `rtol`
+// form the interior [K0, NK).
+static void interior_range(const std::vector<double> &f, int N, int RS, double rtol, int &K0,
+                           int &NK)
+{
+    const int mid = N / 2;
+    auto same = [&](int r) {
+        for (int i = 0; i < RS; ++i) {
+            const double a = f[(size_t)r * RS + i], b = f[(size_t)mid * RS + i];
+            if (std::fabs(a - b) > rtol * std::fabs(b)) return false;
         }
+        return true;
+    };
+    K0 = 0;
+    for (int r = mid - 1; r >= 0; --r)
+        if (!same(r)) { K0 = r + 1; break; }
+    NK = N;
+    for (int r = mid + 1; r < N; ++r)
+        if (!same(r)) { NK = r; break; }
+}
+
+static std::vector<double> compress_rows(const std::vector<double> &f, int N, int RS, int K0, int NK)
+{
+    std::vector<double> out;
+    out.reserve((size_t)(K0 + 1 + N - NK) * RS);
+    for (int r = 0; r < K0; ++r) out.insert(out.end(), f.begin() + (size_t)r * RS, f.begin() + (size_t)(r + 1) * RS);
+    const int c = std::min(K0, N - 1);
+    out.insert(out.end(), f.begin() + (size_t)c * RS, f.begin() + (size_t)(c + 1) * RS);
+    for (int r = NK; r < N; ++r) out.insert(out.end(), f.begin() + (size_t)r * RS, f.begin() + (size_t)(r + 1) * RS);
+    return out;
+}
+
+static inline int row_of(int r, int K0, int NK)
+{
+    return r < K0 ? r : (r >= NK ? K0 + 1 + (r - NK) : K0);
+}
+
+// Forward / backward chunk transfer matrices for the 64 chunks of length m
+// (products of the companion matrices of forward and backward substitution,
+// from the compressed rows the kernels use), and the Hillis-Steele level
+// products: level d of chunk c composes chunks c-2^d+1 .. c (forward) and
+// c .. c+2^d-1 (backward), clipped to the line.
+static void scan_tables(OpHost &o, int N, int P, int m)
+{
+    const int RS = 2 * P + 2, PP = P * P, C = 64, D = 6;
+    std::vector<double> F((size_t)C * PP), B((size_t)C * PP);
+    for (int c = 0; c < C; ++c) {
+        std::vector<double> f(PP, 0.0), b(PP, 0.0);
+        for (int i = 0; i < P; ++i) f[i * P + i] = b[i * P + i] = 1.0;
+        const int r0 = c * m, r1 = std::min(N, r0 + m);
+        for (int r = r0; r < r1; ++r) {           // f <- C_r f
+            const double *L = &o.rows[(size_t)row_of(r, o.K0, o.NK) * RS];
+            std::vector<double> nf(PP, 0.0);
+            for (int j = 0; j < P; ++j) {
+                double s = 0.0;
+                for (int k = 0; k < P; ++k) s -= L[k] * f[k * P + j];
+                nf[j] = s;
+            }
+            for (int i = 1; i < P; ++i)
+                for (int j = 0; j < P; ++j) nf[i * P + j] = f[(i - 1) * P + j];
+            f.swap(nf);
+        }
+        for (int r = r1 - 1; r >= r0; --r) {      // b <- D_r b
+            const double *U = &o.rows[(size_t)row_of(r, o.K0, o.NK) * RS + P];
+            std::vector<double> nb(PP, 0.0);
+            for (int j = 0; j < P; ++j) {
+                double s = 0.0;
+                for (int k = 0; k < P; ++k) s -= U[1 + k] * b[k * P + j];
+                nb[j] = s;
+            }
+            for (int i = 1; i < P; ++i)
+                for (int j = 0; j < P; ++j) nb[i * P + j] = b[(i - 1) * P + j];
+            b.swap(nb);
+        }
+        std::copy(f.begin(), f.end(), F.begin() + (size_t)c * PP);
+        std::copy(b.begin(), b.end(), B.begin() + (size_t)c * PP);
+    }
+    o.tf.assign((size_t)D * C * PP, 0.0);
+    o.tb.assign((size_t)D * C * PP, 0.0);
+    std::copy(F.begin(), F.end(), o.tf.begin());
+    std::copy(B.begin(), B.end(), o.tb.begin());
+    auto mul = [&](const double *a, const double *b, double *out) {
+        for (int i = 0; i < P; ++i)
+            for (int j = 0; j < P; ++j) {
+                double s = 0.0;
+                for (int k = 0; k < P; ++k) s += a[i * P + k] * b[k * P + j];
+                out[i * P + j] = s;
+            }
+    };
+    for (int d = 1; d < D; ++d) {
+        const int off = 1 << (d - 1);
+        const double *pf = &o.tf[(size_t)(d - 1) * C * PP];
+        const double *pb = &o.tb[(size_t)(d - 1) * C * PP];
+        double *nf = &o.tf[(size_t)d * C * PP];
+        double *nb = &o.tb[(size_t)d * C * PP];
+        for (int c = 0; c < C; ++c) {
+            if (c >= off) mul(pf + (size_t)c * PP, pf + (size_t)(c - off) * PP, nf + (size_t)c * PP);
+            else std::copy(pf + (size_t)c * PP, pf + (size_t)(c + 1) * PP, nf + (size_t)c * PP);
+            if (c + off < C) mul(pb + (size_t)c * PP, pb + (size_t)(c + off) * PP, nb + (size_t)c * PP);
+            else std::copy(pb + (size_t)c * PP, pb + (size_t)(c + 1) * PP, nb + (size_t)c * PP);
+        }
+    }
+}
+
+iga_status build_solve_tables(iga_plan *pl)
+{
+    const int P = pl->P, RS = 2 * P + 2, W = 2 * P + 1;
+    // agreement of interior rows: a few ulp of double (factors converge
+    // geometrically; the assembled interior rows are exactly Toeplitz)
+    const double rtol = 1e-15;
+    iga_status st;
+    for (int op = 0; op < NOPS; ++op) {
+        const int dir = op_dir(op), N = dir ? pl->Ny : pl->Nx;
+        std::vector<double> lf((size_t)N * P), uf((size_t)N * (P + 1));
+        IGA_HIP(hipMemcpy(lf.data(), pl->op_lf64[op].ptr, lf.size() * 8, hipMemcpyDeviceToHost));
+        IGA_HIP(hipMemcpy(uf.data(), pl->op_uf64[op].ptr, uf.size() * 8, hipMemcpyDeviceToHost));
+        std::vector<double> f((size_t)N * RS, 0.0), a((size_t)N * RS, 0.0);
+        for (int r = 0; r < N; ++r) {
+            for (int j = 0; j < P; ++j) f[(size_t)r * RS + j] = lf[(size_t)r * P + j];
+            for (int j = 0; j <= P; ++j) f[(size_t)r * RS + P + j] = uf[(size_t)r * (P + 1) + j];
+            for (int j = 0; j < W; ++j) a[(size_t)r * RS + j] = pl->op_band[op][(size_t)r * W + j];
+        }
+        int K0f, NKf, K0a, NKa;
+        interior_range(f, N, RS, rtol, K0f, NKf);
+        interior_range(a, N, RS, rtol, K0a, NKa);
+        OpHost &o = pl->op_host[op];
+        o.K0 = std::max(K0f, K0a);
+        o.NK = std::min(NKf, NKa);
+        if (o.NK <= o.K0) { o.K0 = N; o.NK = N; }   // no interior: keep every row
+        o.rows = compress_rows(f, N, RS, o.K0, o.NK);
+        o.a64 = compress_rows(a, N, RS, o.K0, o.NK);
+        o.nrows = (int)(o.rows.size() / RS);
+        scan_tables(o, N, P, pl->sched[dir].m);
+        if ((st = upload_state(pl, pl->op_rows[op], o.rows))) return st;
+        if ((st = upload_vec<double>(pl->op_a64c[op], o.a64))) return st;
+        if ((st = upload_state(pl, pl->op_tf[op], o.tf))) return st;
+        if ((st = upload_state(pl, pl->op_tb[op], o.tb))) return st;
+    }
+    for (int b = 0; b < NBANDS; ++b) {
+        const int N = b == BAND_BX ? pl->Nx : pl->Ny;
+        std::vector<double> a((size_t)N * RS, 0.0);
+        for (int r = 0; r < N; ++r)
+            for (int j = 0; j < W; ++j) a[(size_t)r * RS + j] = pl->cn_band[b][(size_t)r * W + j];
+        BandHost &o = pl->band_host[b];
+        interior_range(a, N, RS, rtol, o.K0, o.NK);
+        if (o.NK <= o.K0) { o.K0 = N; o.NK = N; }
+        o.rows = compress_rows(a, N, RS, o.K0, o.NK);
+        o.nrows = (int)(o.rows.size() / RS);
+        if ((st = upload_state(pl, pl->band_rows[b], o.rows))) return st;
     }
     return IGA_OK;
 }
@@ -251,84 +400,43 @@ iga_status upload_plan(iga_plan *pl)
 // ---------------------------------------------------------------------------
 // line-solve schedules
 // ---------------------------------------------------------------------------
-static bool fill_schedule(const iga_plan *pl, int dir, int lw, int waves, int mm, Schedule &sc)
+iga_status choose_schedule(iga_plan *pl, int dir, int waves)
 {
-    const int N = dir ? pl->Ny : pl->Nx, p = pl->P;
-    if (!sweep_compiled(p, lw, mm)) return false;
-    if ((waves * 64) % lw) return false;
-    int C = waves * 64 / lw;
-    int m = (N + C - 1) / C;
-    if (m < p) m = p;
-    // the last non-empty chunk must hold at least p rows (neighbour exchange)
-    while (m <= mm) {
-        int used = (N + m - 1) / m;
-        int last = N - (used - 1) * m;
-        if (last >= p) break;
+    const int N = dir ? pl->Ny : pl->Nx, P = pl->P;
+    const int nlines = dir ? pl->Nx : pl->Ny;
+    int m = (N + 63) / 64;
+    if (m < P) m = P;
+    // the last non-empty chunk must hold at least P rows (neighbour exchange)
+    for (;;) {
+        const int used = (N + m - 1) / m;
+        if (N - (used - 1) * m >= P) break;
         ++m;
     }
-    if (m > mm) return false;
-    sc.lw = lw;
-    sc.waves = waves;
+    const int mm = sweep_capacity(m);
+    if (!mm) return fail(IGA_EUNSUPPORTED, "lines of " + std::to_string(N) + " dofs exceed the "
+                                           "compiled register capacity (at most 65 rows per lane)");
+    Schedule &sc = pl->sched[dir];
     sc.mm = mm;
     sc.m = m;
-    sc.chunks = C;
-    int lev = 0;
-    while ((1 << lev) < C) ++lev;
-    sc.levels = lev;
-    if (sweep_lds_bytes(pl, dir, sc) > 160 * 1024) return false;
-    return true;
-}
-
-iga_status choose_schedule(iga_plan *pl, int dir, int lw, int waves)
-{
-    static const int mms[] = {16, 32, 48};
-    Schedule best;
-    bool found = false;
-    if (lw > 0) {
-        for (int mm : mms)
-            if (fill_schedule(pl, dir, lw, waves, mm, best)) { found = true; break; }
-        if (!found)
-            return fail(IGA_EUNSUPPORTED, "line-solve schedule lw=" + std::to_string(lw) +
-                                              " waves=" + std::to_string(waves) +
-                                              " does not fit this line length / precision");
-        pl->sched[dir] = best;
-        return sweep_prepare(pl, dir);
-    }
-    // default heuristic: widest line group that fits, with 16 waves, the
-    // smallest register capacity; narrower for long lines.
-    const int N = dir ? pl->Ny : pl->Nx;
-    const int nlines = dir ? pl->Nx : pl->Ny;
-    static const int lws_long[] = {16, 8, 64};
-    static const int lws_short[] = {64, 16, 8};
-    const int *lws = (nlines >= 256 && N >= 256) ? lws_long : lws_short;
-    for (int i = 0; i < 3 && !found; ++i)
-        for (int w : {16, 8, 4}) {
-            if (found) break;
-            for (int mm : mms)
-                if (fill_schedule(pl, dir, lws[i], w, mm, best)) { found = true; break; }
+    const int bound = mm <= 17 ? 16 : (mm <= 33 ? 8 : 4);
+    if (waves <= 0) {
+        // widest workgroup that fits LDS and still gives >= 256 workgroups
+        waves = 1;
+        for (int w : {16, 8, 4, 2}) {
+            if (w > bound || sweep_lds_bytes(pl, dir, w) > 160 * 1024) continue;
+            if ((nlines + w - 1) / w >= 256 || w == 2) { waves = w; break; }
         }
-    if (!found) return fail(IGA_EUNSUPPORTED, "no compiled line-solve schedule fits lines of " +
-                                                  std::to_string(N) + " dofs");
-    pl->sched[dir] = best;
-    return sweep_prepare(pl, dir);
-}
-
-OpDev op_dev(const iga_plan *pl, int op)
-{
-    OpDev o;
-    if (pl->fp32) {
-        o.lf = pl->op_lf32[op].ptr;
-        o.uf = pl->op_uf32[op].ptr;
-        o.tf = pl->op_tf32[op].ptr;
-        o.tb = pl->op_tb32[op].ptr;
-    } else {
-        o.lf = pl->op_lf64[op].ptr;
-        o.uf = pl->op_uf64[op].ptr;
-        o.tf = pl->op_tf64[op].ptr;
-        o.tb = pl->op_tb64[op].ptr;
+        if (dir == 0 && waves < 4 && bound >= 4 && sweep_lds_bytes(pl, dir, 4) <= 160 * 1024)
+            waves = 4;
     }
-    o.a64 = pl->op_a64[op].as<double>();
-    return o;
+    if (sweep_lds_bytes(pl, dir, waves) > 160 * 1024)
+        return fail(IGA_EUNSUPPORTED, "line-solve workgroup of " + std::to_string(waves) +
+                                          " lines does not fit in LDS");
+    if (waves > bound)
+        return fail(IGA_EUNSUPPORTED, "at most " + std::to_string(bound) +
+                                          " lines per workgroup for this line length");
+    sc.waves = waves;
+    return sweep_prepare(pl, dir);
 }
 
 }  // namespace iga

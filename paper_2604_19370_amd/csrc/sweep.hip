@@ -1,49 +1,58 @@
-// sweep.hip -- dispatch of the batched line-solve kernels (sweep_kernels.h).
+// sweep.hip -- launch of the wavefront-per-line banded solves (sweep_kernels.h).
 #include "sweep_kernels.h"
 
 namespace iga {
 
-// ---------------------------------------------------------------------------
-// dispatch
-// ---------------------------------------------------------------------------
-static SweepFn pick_fn(bool fp32, int P, int lw, int mm, bool diry)
+static SweepFn pick_fn(bool fp32, int P, int mm, bool diry)
 {
     if (fp32) {
-        if (P == 2) return pick_sweep_f2(lw, mm, diry);
-        if (P == 3) return pick_sweep_f3(lw, mm, diry);
+        if (P == 2) return pick_sweep_f2(mm, diry);
+        if (P == 3) return pick_sweep_f3(mm, diry);
     } else {
-        if (P == 2) return pick_sweep_d2(lw, mm, diry);
-        if (P == 3) return pick_sweep_d3(lw, mm, diry);
+        if (P == 2) return pick_sweep_d2(mm, diry);
+        if (P == 3) return pick_sweep_d3(mm, diry);
     }
     return nullptr;
 }
 
-bool sweep_compiled(int P, int lw, int mm)
+int sweep_capacity(int m)
 {
-    return pick_fn(false, P, lw, mm, false) != nullptr;
+    static const int caps[] = {4, 8, 12, 17, 33, 48, 65};
+    for (int c : caps)
+        if (m <= c) return c;
+    return 0;
 }
 
-size_t sweep_lds_bytes(const iga_plan *pl, int dir, const Schedule &sc)
+static size_t align16(size_t b) { return (b + 15) & ~(size_t)15; }
+
+static size_t stage_stride(int N) { return (size_t)(N | 1); }
+
+// LDS of one workgroup: the staged lines plus the largest table set a job of
+// this direction stages (two factored operators and one band).
+size_t sweep_lds_bytes(const iga_plan *pl, int dir, int waves)
 {
     const size_t w = pl->wsize;
-    size_t scan = (size_t)sc.chunks * sc.lw * pl->P * w;
-    size_t xch = (size_t)sc.chunks * sc.lw * 2 * pl->P * w;
-    size_t b = scan + xch;
-    if (dir == 1) {
-        size_t stage = (size_t)sc.lw * pl->Ny * w;
-        b = std::max(b, stage);
-    }
+    const int N = dir ? pl->Ny : pl->Nx;
+    const int RS = 2 * pl->P + 2;
+    size_t b = align16((size_t)waves * stage_stride(N) * w);
+    int maxrows = 0;
+    for (int op = 0; op < NOPS; ++op)
+        if (op_dir(op) == dir) maxrows = std::max(maxrows, pl->op_host[op].nrows);
+    for (int bd = 0; bd < NBANDS; ++bd)
+        if ((bd == BAND_BX ? 0 : 1) == dir) maxrows = std::max(maxrows, pl->band_host[bd].nrows);
+    if (maxrows == 0) maxrows = 96;   // before factorisation: a typical interior-compressed size
+    const size_t op_bytes = align16((size_t)maxrows * RS * w) + (pl->fp32 ? (size_t)maxrows * RS * 8 : 0);
+    b += 2 * op_bytes + align16((size_t)maxrows * RS * w);
     return b;
 }
 
 iga_status sweep_prepare(const iga_plan *pl, int dir)
 {
     const Schedule &sc = pl->sched[dir];
-    SweepFn fn = pick_fn(pl->fp32, pl->P, sc.lw, sc.mm, dir == 1);
+    SweepFn fn = pick_fn(pl->fp32, pl->P, sc.mm, dir == 1);
     if (!fn) return fail(IGA_EUNSUPPORTED, "line-solve kernel not compiled for this schedule");
-    const size_t lds = sweep_lds_bytes(pl, dir, sc);
     IGA_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(fn),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+                                hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
     return IGA_OK;
 }
 
@@ -51,21 +60,32 @@ iga_status launch_sweep(const iga_plan *pl, int dir, const SweepJob *jobs, int n
 {
     if (njobs < 1 || njobs > MAXJOBS) return fail(IGA_EINVAL, "bad sweep job count");
     const Schedule &sc = pl->sched[dir];
-    SweepFn fn = pick_fn(pl->fp32, pl->P, sc.lw, sc.mm, dir == 1);
+    SweepFn fn = pick_fn(pl->fp32, pl->P, sc.mm, dir == 1);
     if (!fn) return fail(IGA_EUNSUPPORTED, "line-solve kernel not compiled for this schedule");
     SweepParams prm;
     std::memset(&prm, 0, sizeof prm);
-    for (int j = 0; j < njobs; ++j) prm.jobs[j] = jobs[j];
-    for (int op = 0; op < NOPS; ++op) prm.ops[op] = op_dev(pl, op);
-    for (int b = 0; b < NBANDS; ++b) prm.bands[b] = pl->cn_dev[b].ptr;
+    for (int j = 0; j < njobs; ++j) {
+        prm.jobs[j] = jobs[j];
+        if (jobs[j].op0 >= 0 && op_dir(jobs[j].op0) != dir) return fail(IGA_EINVAL, "operator direction");
+        if (jobs[j].op1 >= 0 && op_dir(jobs[j].op1) != dir) return fail(IGA_EINVAL, "operator direction");
+    }
+    for (int op = 0; op < NOPS; ++op) {
+        const OpHost &o = pl->op_host[op];
+        prm.ops[op] = OpTab{pl->op_rows[op].ptr, pl->op_a64c[op].as<double>(), pl->op_tf[op].ptr,
+                            pl->op_tb[op].ptr, o.K0, o.NK, o.nrows};
+    }
+    for (int b = 0; b < NBANDS; ++b) {
+        const BandHost &o = pl->band_host[b];
+        prm.bands[b] = BandTab{pl->band_rows[b].ptr, o.K0, o.NK, o.nrows};
+    }
     prm.N = dir ? pl->Ny : pl->Nx;
     prm.nlines = dir ? pl->Nx : pl->Ny;
     prm.ld = pl->Ny;
     prm.m = sc.m;
-    prm.C = sc.chunks;
-    prm.D = sc.levels;
-    const int nblk = (prm.nlines + sc.lw - 1) / sc.lw;
-    const size_t lds = sweep_lds_bytes(pl, dir, sc);
+    prm.Ns = (int)stage_stride(prm.N);
+    const int nblk = (prm.nlines + sc.waves - 1) / sc.waves;
+    const size_t lds = sweep_lds_bytes(pl, dir, sc.waves);
+    if (lds > 160 * 1024) return fail(IGA_EUNSUPPORTED, "line-solve tables do not fit in LDS");
     hipLaunchKernelGGL(fn, dim3(nblk, njobs), dim3(sc.waves * 64), lds, s, prm);
     IGA_HIP(hipGetLastError());
     return IGA_OK;

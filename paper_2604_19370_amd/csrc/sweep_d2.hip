@@ -2,5 +2,5 @@
 #include "sweep_kernels.h"
 
 namespace iga {
-SweepFn pick_sweep_d2(int lw, int mm, bool diry) { return pick_lw_mm<double, 2>(lw, mm, diry); }
+SweepFn pick_sweep_d2(int mm, bool diry) { return pick_mm<double, 2>(mm, diry); }
 }  // namespace iga

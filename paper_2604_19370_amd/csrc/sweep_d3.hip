@@ -2,5 +2,5 @@
 #include "sweep_kernels.h"
 
 namespace iga {
-SweepFn pick_sweep_d3(int lw, int mm, bool diry) { return pick_lw_mm<double, 3>(lw, mm, diry); }
+SweepFn pick_sweep_d3(int mm, bool diry) { return pick_mm<double, 3>(mm, diry); }
 }  // namespace iga

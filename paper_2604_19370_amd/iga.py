@@ -75,8 +75,8 @@ def lib() -> ctypes.CDLL:
         L.iga_line_solve.argtypes = [vp, i32, i32, vp, vp]
         L.iga_step.argtypes = [vp, vp, vp, vp]
         L.iga_run.argtypes = [vp, vp, vp, i64, vp]
-        L.iga_plan_schedule.argtypes = [vp, i32] + [ctypes.POINTER(i32)] * 4
-        L.iga_plan_set_schedule.argtypes = [vp, i32, i32, i32, vp]
+        L.iga_plan_schedule.argtypes = [vp, i32] + [ctypes.POINTER(i32)] * 3
+        L.iga_plan_set_schedule.argtypes = [vp, i32, i32]
         L.iga_plan_set_assembly_rows.argtypes = [vp, i32]
         L.iga_last_error.argtypes = []
         L.iga_last_error.restype = ctypes.c_char_p
@@ -207,14 +207,13 @@ class Plan:
                              int(nsteps), _stream(stream)), "iga_run")
 
     def schedule(self, dir):
-        v = [ctypes.c_int32() for _ in range(4)]
+        v = [ctypes.c_int32() for _ in range(3)]
         _check(lib().iga_plan_schedule(self._h, int(dir), *[ctypes.byref(x) for x in v]),
                "iga_plan_schedule")
-        return dict(lw=v[0].value, m=v[1].value, chunks=v[2].value, waves=v[3].value)
+        return dict(waves=v[0].value, m=v[1].value, capacity=v[2].value)
 
-    def set_schedule(self, dir, lw, waves, stream=None):
-        _check(lib().iga_plan_set_schedule(self._h, int(dir), int(lw), int(waves),
-                                           _stream(stream)), "iga_plan_set_schedule")
+    def set_schedule(self, dir, waves):
+        _check(lib().iga_plan_set_schedule(self._h, int(dir), int(waves)), "iga_plan_set_schedule")
 
     def set_assembly_rows(self, rows):
         _check(lib().iga_plan_set_assembly_rows(self._h, int(rows)), "iga_plan_set_assembly_rows")
