@@ -139,9 +139,13 @@ def main():
     for prec in ("fp32", "fp64"):
         pl = iga.Plan.from_scenario(sc, precision=prec)
         pl.factor()
+        Tt = torch.tensor(sc.T0, dtype=pl.dtype, device="cuda")
+        Ft = torch.tensor(sc.fuel0, dtype=pl.dtype, device="cuda")
+        pl.autotune(Tt, Ft, reps=10)          # untimed: picks tiles / workgroup widths
+        del Tt, Ft
         wall, ev, T, F = time_steps(pl, sc, args.steps, args.warmup, torch)
         res[prec] = dict(wall=wall, ev=ev, dofs=sc.ndof * args.steps / wall,
-                         sched=[pl.schedule(0), pl.schedule(1)])
+                         sched=[pl.schedule(0), pl.schedule(1), {"assembly_rows": pl.assembly_rows}])
         ktimes[prec] = kernel_times(pl, sc, args.kernel_reps, torch)
         pl.close()
 

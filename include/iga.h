@@ -169,18 +169,29 @@ iga_status iga_step(iga_plan *plan, void *T, void *fuel, void *stream);
 iga_status iga_run(iga_plan *plan, void *T, void *fuel, int64_t nsteps, void *stream);
 
 /* Line-solve schedule of direction dir: wavefronts (= lines) per workgroup,
- * rows per lane m (each line is split into 64 chunks of m rows) and the
- * compiled register capacity used for m. */
+ * rows per lane m (each line is split into 64 chunks of m rows), the compiled
+ * register capacity used for m, and the largest compressed coefficient table
+ * (rows kept per operator after merging the identical interior rows).  Any
+ * output pointer may be NULL. */
 iga_status iga_plan_schedule(const iga_plan *plan, int32_t dir, int32_t *waves, int32_t *m,
-                             int32_t *capacity);
+                             int32_t *capacity, int32_t *table_rows);
 
-/* Choose the number of lines per workgroup for direction dir (autotuning):
- * waves in {1, 2, 4, 8, 16}.  IGA_EUNSUPPORTED if the workgroup does not fit
- * the register or LDS budget for this line length. */
+/* Choose the number of lines per workgroup for direction dir: waves in
+ * {1, 2, 4, 8, 16}.  IGA_EUNSUPPORTED if the workgroup does not fit the
+ * register or LDS budget for this line length. */
 iga_status iga_plan_set_schedule(iga_plan *plan, int32_t dir, int32_t waves);
 
 /* Assembly schedule: element rows marched per wavefront (>= 1). */
 iga_status iga_plan_set_assembly_rows(iga_plan *plan, int32_t rows);
+int32_t iga_plan_assembly_rows(const iga_plan *plan);
+
+/* Autotuner: times, with HIP events on `stream`, the assembly of the first
+ * substep for several element-row tiles and the line solves of each direction
+ * for every workgroup width, on the plan's scratch buffers (T and fuel are
+ * only read), and keeps the fastest of each.  Synchronises `stream`; must
+ * follow iga_factor_1d.  reps >= 1 launches per candidate. */
+iga_status iga_autotune(iga_plan *plan, const void *T, const void *fuel, int32_t reps,
+                        void *stream);
 
 /* Thread-local description of the last error ("" if none). */
 const char *iga_last_error(void);

@@ -143,6 +143,28 @@ static iga_status capture(iga_plan *pl, GraphEntry &g, void *T, void *fuel, int6
     return IGA_OK;
 }
 
+// Time `reps` launches of fn between HIP events on s; returns ms per launch
+// (negative on failure).
+template <typename F> static float time_launches(hipStream_t s, int reps, F &&fn)
+{
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess) return -1.f;
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return -1.f;
+    }
+    float ms = -1.f;
+    bool ok = fn() == IGA_OK;   // warm-up
+    ok = ok && hipEventRecord(e0, s) == hipSuccess;
+    for (int i = 0; i < reps && ok; ++i) ok = fn() == IGA_OK;
+    ok = ok && hipEventRecord(e1, s) == hipSuccess && hipEventSynchronize(e1) == hipSuccess;
+    if (ok && hipEventElapsedTime(&ms, e0, e1) == hipSuccess) ms /= reps;
+    else ms = -1.f;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return ms;
+}
+
 }  // namespace iga
 
 using namespace iga;
@@ -310,7 +332,7 @@ iga_status iga_run(iga_plan *plan, void *T, void *fuel, int64_t nsteps, void *st
 }
 
 iga_status iga_plan_schedule(const iga_plan *plan, int32_t dir, int32_t *waves, int32_t *m,
-                             int32_t *capacity)
+                             int32_t *capacity, int32_t *table_rows)
 {
     if (!plan) return fail(IGA_EINVAL, "plan is NULL");
     if (dir != 0 && dir != 1) return fail(IGA_EINVAL, "dir must be 0 or 1");
@@ -318,6 +340,12 @@ iga_status iga_plan_schedule(const iga_plan *plan, int32_t dir, int32_t *waves, 
     if (waves) *waves = sc.waves;
     if (m) *m = sc.m;
     if (capacity) *capacity = sc.mm;
+    if (table_rows) {
+        int r = 0;
+        for (int op = 0; op < NOPS; ++op)
+            if (op_dir(op) == dir) r = std::max(r, plan->op_host[op].nrows);
+        *table_rows = r;
+    }
     return IGA_OK;
 }
 
@@ -343,6 +371,67 @@ iga_status iga_plan_set_assembly_rows(iga_plan *plan, int32_t rows)
     if (rows < 1) return fail(IGA_EINVAL, "rows must be >= 1");
     plan->asm_rows = rows;
     plan->graph.reset();
+    return IGA_OK;
+}
+
+int32_t iga_plan_assembly_rows(const iga_plan *plan) { return plan ? plan->asm_rows : 0; }
+
+iga_status iga_autotune(iga_plan *plan, const void *T, const void *fuel, int32_t reps, void *stream)
+{
+    if (!plan) return fail(IGA_EINVAL, "plan is NULL");
+    iga_status st;
+    if ((st = check_field(T, "T")) || (st = check_field(fuel, "fuel"))) return st;
+    if (reps < 1) return fail(IGA_EINVAL, "reps must be >= 1");
+    if (!plan->factored) return fail(IGA_ESTATE, "iga_factor_1d has not been called");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    void *R = plan->scratch_r.ptr, *RF = plan->scratch_rf.ptr;
+    DevBuf out;   // two output fields, so the two jobs of a launch never share one
+    IGA_HIP(out.alloc(2 * plan->ndof * plan->wsize));
+    void *out2 = out.as<char>() + plan->ndof * plan->wsize;
+    // assembly: element rows marched per wavefront
+    {
+        int best = plan->asm_rows;
+        float best_ms = 1e30f;
+        for (int rows : {4, 8, 16, 32, 64}) {
+            if (rows > plan->Nx && rows != 4) continue;
+            plan->asm_rows = rows;
+            float ms = time_launches(s, reps, [&] { return launch_assemble(plan, 0, T, fuel, R, RF, s); });
+            if (ms >= 0 && ms < best_ms) { best_ms = ms; best = rows; }
+        }
+        plan->asm_rows = best;
+        if ((st = launch_assemble(plan, 0, T, fuel, R, RF, s))) return st;
+    }
+    // line solves: lines per workgroup, timed on the step's own jobs
+    const void *bT = plan->delta ? T : nullptr;
+    const int add = plan->delta ? 1 : 0;
+    for (int dir = 0; dir < 2; ++dir) {
+        SweepJob jobs[2];
+        int nj;
+        if (dir == 0) {
+            jobs[0] = SweepJob{R, out.ptr, OP_AX, -1, -1, nullptr, 0};
+            jobs[1] = SweepJob{RF, out2, OP_MX, -1, -1, nullptr, 0};
+            nj = 2;
+        } else if (plan->d.scheme == IGA_STRANG_CN) {
+            jobs[0] = SweepJob{R, out.ptr, OP_MY, BAND_BY, OP_AY, bT, add};
+            nj = 1;
+        } else {
+            jobs[0] = SweepJob{R, out.ptr, OP_MY, -1, -1, bT, 0};
+            nj = 1;
+        }
+        Schedule keep = plan->sched[dir];
+        int best = keep.waves;
+        float best_ms = 1e30f;
+        for (int w : {1, 2, 4, 8, 16}) {
+            if (choose_schedule(plan, dir, w) != IGA_OK) continue;
+            float ms = time_launches(s, reps, [&] { return launch_sweep(plan, dir, jobs, nj, s); });
+            if (ms >= 0 && ms < best_ms) { best_ms = ms; best = w; }
+        }
+        plan->sched[dir] = keep;
+        if ((st = choose_schedule(plan, dir, best))) return st;
+    }
+    IGA_HIP(hipStreamSynchronize(s));
+    plan->graph.reset();
+    set_error("");
     return IGA_OK;
 }
 

@@ -136,25 +136,35 @@ __global__ __launch_bounds__(256) void k_assemble(AsmParams<T> a)
         fetch(X0 - P + s, c0, c1, f0, f1);
         ytransform(c0, c1, f0, f1, tv[s], td[s], tf[s]);
     }
-    T nc0, nc1, nf0, nf1;   // row ex + P, fetched one iteration ahead
+    // coefficient rows are fetched two element rows ahead, the element row's
+    // x basis table one row ahead, so neither load latency is exposed
+    T nc0, nc1, nf0, nf1, mc0, mc1, mf0, mf1;
     fetch(X0, nc0, nc1, nf0, nf1);
+    fetch(X0 + 1, mc0, mc1, mf0, mf1);
+    auto xtab = [&](int ex, T(&v)[Q][Q], T(&dv)[Q][Q], T(&w)[Q]) {
+        const int e = ex < 0 ? 0 : (ex >= a.nel_x ? a.nel_x - 1 : ex);
+        const T *bxe = a.bx + (size_t)e * 2 * Q * Q;
+#pragma unroll
+        for (int i = 0; i < Q; ++i)
+#pragma unroll
+            for (int q = 0; q < Q; ++q) {
+                v[i][q] = bxe[i * Q + q];
+                dv[i][q] = bxe[Q * Q + i * Q + q];
+            }
+#pragma unroll
+        for (int q = 0; q < Q; ++q) w[q] = a.wx[(size_t)e * Q + q];
+    };
+    T bxv[Q][Q], bxd[Q][Q], wxr[Q];
+    xtab(X0 - P, bxv, bxd, wxr);
 
     for (int ex = X0 - P; ex < X1; ++ex) {
         const T c0 = nc0, c1 = nc1, f0 = nf0, f1 = nf1;
-        fetch(ex + P + 1, nc0, nc1, nf0, nf1);
+        nc0 = mc0; nc1 = mc1; nf0 = mf0; nf1 = mf1;
+        fetch(ex + P + 2, mc0, mc1, mf0, mf1);
+        T nbxv[Q][Q], nbxd[Q][Q], nwxr[Q];
+        xtab(ex + 1, nbxv, nbxd, nwxr);
         ytransform(c0, c1, f0, f1, tv[P], td[P], tf[P]);
         if (ex >= 0 && ex < a.nel_x) {
-            const T *bxe = a.bx + (size_t)ex * 2 * Q * Q;
-            T bxv[Q][Q], bxd[Q][Q], wxr[Q];
-#pragma unroll
-            for (int i = 0; i < Q; ++i)
-#pragma unroll
-                for (int q = 0; q < Q; ++q) {
-                    bxv[i][q] = bxe[i * Q + q];
-                    bxd[i][q] = bxe[Q * Q + i * Q + q];
-                }
-#pragma unroll
-            for (int q = 0; q < Q; ++q) wxr[q] = a.wx[(size_t)ex * Q + q];
 #pragma unroll
             for (int qx = 0; qx < Q; ++qx) {
 #pragma unroll
@@ -217,6 +227,15 @@ __global__ __launch_bounds__(256) void k_assemble(AsmParams<T> a)
             }
         }
         // roll the windows
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+#pragma unroll
+            for (int q = 0; q < Q; ++q) {
+                bxv[i][q] = nbxv[i][q];
+                bxd[i][q] = nbxd[i][q];
+            }
+            wxr[i] = nwxr[i];
+        }
 #pragma unroll
         for (int s = 0; s < P; ++s)
 #pragma unroll

@@ -71,8 +71,8 @@ struct Schedule {
 //   rows[i*RS + j]      j < P: L(r, r-1-j);  rows[i*RS + P] = 1/U(r,r);
 //                       rows[i*RS + P + 1 + j] = U(r, r+1+j)/U(r,r)
 //   a64[i*RS + j]       A(r, r-P+j), j <= 2P (the operator, for refinement)
-//   tf[(d*64 + c)*P*P]  forward transfer of chunks c-2^d+1 .. c
-//   tb[(d*64 + c)*P*P]  backward transfer of chunks c .. c+2^d-1
+//   tf[c*P*P]           forward transfer matrix of chunk c
+//   tb[c*P*P]           backward transfer matrix of chunk c
 struct OpHost {
     int K0 = 0, NK = 0, nrows = 0;
     std::vector<double> rows, a64, tf, tb;

@@ -276,16 +276,17 @@ static std::vector<double> compress_rows(const std::vector<double> &f, int N, in
     return out;
 }
 
-static inline int row_of(int r, int K0, int NK)
+// table row of line row r (the kernels' mapping): rows below K0 and from NK
+// on are stored, the interior shares row K0, padding rows map to the last row
+static inline int row_of(int r, int K0, int NK, int nrows)
 {
-    return r < K0 ? r : (r >= NK ? K0 + 1 + (r - NK) : K0);
+    return std::min(std::min(r, K0) + std::max(0, r - NK + 1), nrows - 1);
 }
 
 // Forward / backward chunk transfer matrices for the 64 chunks of length m
 // (products of the companion matrices of forward and backward substitution,
-// from the compressed rows the kernels use), and the Hillis-Steele level
-// products: level d of chunk c composes chunks c-2^d+1 .. c (forward) and
-// c .. c+2^d-1 (backward), clipped to the line.
+// from the compressed rows the kernels use; rows past N are the identity
+// padding rows).  The line-solve kernels compose them along their scan.
 static void scan_tables(OpHost &o, int N, int P, int m)
 {
     const int RS = 2 * P + 2, PP = P * P, C = 64, D = 6;
@@ -293,9 +294,10 @@ static void scan_tables(OpHost &o, int N, int P, int m)
     for (int c = 0; c < C; ++c) {
         std::vector<double> f(PP, 0.0), b(PP, 0.0);
         for (int i = 0; i < P; ++i) f[i * P + i] = b[i * P + i] = 1.0;
-        const int r0 = c * m, r1 = std::min(N, r0 + m);
+        const int r0 = c * m, r1 = r0 + m;
+        (void)N;
         for (int r = r0; r < r1; ++r) {           // f <- C_r f
-            const double *L = &o.rows[(size_t)row_of(r, o.K0, o.NK) * RS];
+            const double *L = &o.rows[(size_t)row_of(r, o.K0, o.NK, o.nrows) * RS];
             std::vector<double> nf(PP, 0.0);
             for (int j = 0; j < P; ++j) {
                 double s = 0.0;
@@ -307,7 +309,7 @@ static void scan_tables(OpHost &o, int N, int P, int m)
             f.swap(nf);
         }
         for (int r = r1 - 1; r >= r0; --r) {      // b <- D_r b
-            const double *U = &o.rows[(size_t)row_of(r, o.K0, o.NK) * RS + P];
+            const double *U = &o.rows[(size_t)row_of(r, o.K0, o.NK, o.nrows) * RS + P];
             std::vector<double> nb(PP, 0.0);
             for (int j = 0; j < P; ++j) {
                 double s = 0.0;
@@ -321,31 +323,9 @@ static void scan_tables(OpHost &o, int N, int P, int m)
         std::copy(f.begin(), f.end(), F.begin() + (size_t)c * PP);
         std::copy(b.begin(), b.end(), B.begin() + (size_t)c * PP);
     }
-    o.tf.assign((size_t)D * C * PP, 0.0);
-    o.tb.assign((size_t)D * C * PP, 0.0);
-    std::copy(F.begin(), F.end(), o.tf.begin());
-    std::copy(B.begin(), B.end(), o.tb.begin());
-    auto mul = [&](const double *a, const double *b, double *out) {
-        for (int i = 0; i < P; ++i)
-            for (int j = 0; j < P; ++j) {
-                double s = 0.0;
-                for (int k = 0; k < P; ++k) s += a[i * P + k] * b[k * P + j];
-                out[i * P + j] = s;
-            }
-    };
-    for (int d = 1; d < D; ++d) {
-        const int off = 1 << (d - 1);
-        const double *pf = &o.tf[(size_t)(d - 1) * C * PP];
-        const double *pb = &o.tb[(size_t)(d - 1) * C * PP];
-        double *nf = &o.tf[(size_t)d * C * PP];
-        double *nb = &o.tb[(size_t)d * C * PP];
-        for (int c = 0; c < C; ++c) {
-            if (c >= off) mul(pf + (size_t)c * PP, pf + (size_t)(c - off) * PP, nf + (size_t)c * PP);
-            else std::copy(pf + (size_t)c * PP, pf + (size_t)(c + 1) * PP, nf + (size_t)c * PP);
-            if (c + off < C) mul(pb + (size_t)c * PP, pb + (size_t)(c + off) * PP, nb + (size_t)c * PP);
-            else std::copy(pb + (size_t)c * PP, pb + (size_t)(c + 1) * PP, nb + (size_t)c * PP);
-        }
-    }
+    o.tf = F;
+    o.tb = B;
+    (void)D;
 }
 
 iga_status build_solve_tables(iga_plan *pl)
@@ -375,6 +355,13 @@ iga_status build_solve_tables(iga_plan *pl)
         if (o.NK <= o.K0) { o.K0 = N; o.NK = N; }   // no interior: keep every row
         o.rows = compress_rows(f, N, RS, o.K0, o.NK);
         o.a64 = compress_rows(a, N, RS, o.K0, o.NK);
+        // identity row for the padding rows past N
+        std::vector<double> id(RS, 0.0);
+        id[P] = 1.0;
+        o.rows.insert(o.rows.end(), id.begin(), id.end());
+        id.assign(RS, 0.0);
+        id[P] = 1.0;
+        o.a64.insert(o.a64.end(), id.begin(), id.end());
         o.nrows = (int)(o.rows.size() / RS);
         scan_tables(o, N, P, pl->sched[dir].m);
         if ((st = upload_state(pl, pl->op_rows[op], o.rows))) return st;
@@ -391,6 +378,7 @@ iga_status build_solve_tables(iga_plan *pl)
         interior_range(a, N, RS, rtol, o.K0, o.NK);
         if (o.NK <= o.K0) { o.K0 = N; o.NK = N; }
         o.rows = compress_rows(a, N, RS, o.K0, o.NK);
+        o.rows.insert(o.rows.end(), (size_t)RS, 0.0);   // zero row for the padding
         o.nrows = (int)(o.rows.size() / RS);
         if ((st = upload_state(pl, pl->band_rows[b], o.rows))) return st;
     }
@@ -404,15 +392,9 @@ iga_status choose_schedule(iga_plan *pl, int dir, int waves)
 {
     const int N = dir ? pl->Ny : pl->Nx, P = pl->P;
     const int nlines = dir ? pl->Nx : pl->Ny;
-    int m = (N + 63) / 64;
-    if (m < P) m = P;
-    // the last non-empty chunk must hold at least P rows (neighbour exchange)
-    for (;;) {
-        const int used = (N + m - 1) / m;
-        if (N - (used - 1) * m >= P) break;
-        ++m;
-    }
-    const int mm = sweep_capacity(m);
+    // each lane holds mm rows; the line is padded to 64 mm rows
+    const int mm = sweep_capacity(std::max((N + 63) / 64, P));
+    const int m = mm;
     if (!mm) return fail(IGA_EUNSUPPORTED, "lines of " + std::to_string(N) + " dofs exceed the "
                                            "compiled register capacity (at most 65 rows per lane)");
     Schedule &sc = pl->sched[dir];

@@ -25,23 +25,26 @@ int sweep_capacity(int m)
 
 static size_t align16(size_t b) { return (b + 15) & ~(size_t)15; }
 
-static size_t stage_stride(int N) { return (size_t)(N | 1); }
+static size_t stage_stride(int N, int dir) { return dir ? (size_t)N : (size_t)(N | 1); }
 
 // LDS of one workgroup: the staged lines plus the largest table set a job of
-// this direction stages (two factored operators and one band).
+// this direction stages (two factored operators with their refinement rows and
+// scan tables, and one band).
 size_t sweep_lds_bytes(const iga_plan *pl, int dir, int waves)
 {
     const size_t w = pl->wsize;
     const int N = dir ? pl->Ny : pl->Nx;
-    const int RS = 2 * pl->P + 2;
-    size_t b = align16((size_t)waves * stage_stride(N) * w);
+    const int P = pl->P, RS = 2 * P + 2;
+    const size_t scan = (size_t)64 * P * P * w;
+    size_t b = align16((size_t)waves * stage_stride(N, dir) * w);
     int maxrows = 0;
     for (int op = 0; op < NOPS; ++op)
         if (op_dir(op) == dir) maxrows = std::max(maxrows, pl->op_host[op].nrows);
     for (int bd = 0; bd < NBANDS; ++bd)
         if ((bd == BAND_BX ? 0 : 1) == dir) maxrows = std::max(maxrows, pl->band_host[bd].nrows);
     if (maxrows == 0) maxrows = 96;   // before factorisation: a typical interior-compressed size
-    const size_t op_bytes = align16((size_t)maxrows * RS * w) + (pl->fp32 ? (size_t)maxrows * RS * 8 : 0);
+    const size_t op_bytes = align16((size_t)maxrows * RS * w) +
+                            (pl->fp32 ? align16((size_t)maxrows * RS * 8) : 0) + 2 * align16(scan);
     b += 2 * op_bytes + align16((size_t)maxrows * RS * w);
     return b;
 }
@@ -82,7 +85,7 @@ iga_status launch_sweep(const iga_plan *pl, int dir, const SweepJob *jobs, int n
     prm.nlines = dir ? pl->Nx : pl->Ny;
     prm.ld = pl->Ny;
     prm.m = sc.m;
-    prm.Ns = (int)stage_stride(prm.N);
+    prm.Ns = (int)stage_stride(prm.N, dir);
     const int nblk = (prm.nlines + sc.waves - 1) / sc.waves;
     const size_t lds = sweep_lds_bytes(pl, dir, sc.waves);
     if (lds > 160 * 1024) return fail(IGA_EUNSUPPORTED, "line-solve tables do not fit in LDS");

@@ -23,7 +23,7 @@ WIND_CONST, WIND_SINCOS = 0, 1
 EXPORTED = ("iga_default_coeffs", "iga_plan_create", "iga_plan_destroy", "iga_plan_dims",
             "iga_factor_1d", "iga_assemble_rhs", "iga_line_solve", "iga_step", "iga_run",
             "iga_plan_schedule", "iga_plan_set_schedule", "iga_plan_set_assembly_rows",
-            "iga_last_error")
+            "iga_plan_assembly_rows", "iga_autotune", "iga_last_error")
 
 _COEFF_NAMES = ("c_adv", "c_diff", "c_react", "c_nld", "c_ign", "t_ig", "fuel_thr", "t_act",
                 "c_forcing", "c_rad", "fuel_rate")
@@ -75,13 +75,17 @@ def lib() -> ctypes.CDLL:
         L.iga_line_solve.argtypes = [vp, i32, i32, vp, vp]
         L.iga_step.argtypes = [vp, vp, vp, vp]
         L.iga_run.argtypes = [vp, vp, vp, i64, vp]
-        L.iga_plan_schedule.argtypes = [vp, i32] + [ctypes.POINTER(i32)] * 3
+        L.iga_plan_schedule.argtypes = [vp, i32] + [ctypes.POINTER(i32)] * 4
         L.iga_plan_set_schedule.argtypes = [vp, i32, i32]
         L.iga_plan_set_assembly_rows.argtypes = [vp, i32]
+        L.iga_plan_assembly_rows.argtypes = [vp]
+        L.iga_plan_assembly_rows.restype = i32
+        L.iga_autotune.argtypes = [vp, vp, vp, i32, vp]
         L.iga_last_error.argtypes = []
         L.iga_last_error.restype = ctypes.c_char_p
         for name in EXPORTED[1:-1]:
-            getattr(L, name).restype = ctypes.c_int
+            if name != "iga_plan_assembly_rows":
+                getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -207,10 +211,18 @@ class Plan:
                              int(nsteps), _stream(stream)), "iga_run")
 
     def schedule(self, dir):
-        v = [ctypes.c_int32() for _ in range(3)]
+        v = [ctypes.c_int32() for _ in range(4)]
         _check(lib().iga_plan_schedule(self._h, int(dir), *[ctypes.byref(x) for x in v]),
                "iga_plan_schedule")
-        return dict(waves=v[0].value, m=v[1].value, capacity=v[2].value)
+        return dict(waves=v[0].value, m=v[1].value, capacity=v[2].value, table_rows=v[3].value)
+
+    @property
+    def assembly_rows(self) -> int:
+        return int(lib().iga_plan_assembly_rows(self._h))
+
+    def autotune(self, T, fuel, reps=20, stream=None):
+        _check(lib().iga_autotune(self._h, self._field(T, "T"), self._field(fuel, "fuel"),
+                                  int(reps), _stream(stream)), "iga_autotune")
 
     def set_schedule(self, dir, waves):
         _check(lib().iga_plan_set_schedule(self._h, int(dir), int(waves)), "iga_plan_set_schedule")

@@ -233,3 +233,19 @@ def test_nonfinite_detection():
     t2, f2 = dev(sc.T0), dev(sc.fuel0)
     pl.run(t2, f2, 4)
     assert torch.isfinite(t2).all()
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", TOL64), ("fp32", TOL32)])
+def test_autotune_then_step_parity(precision, tol):
+    sc = inputs.small_case(12, 260, 200, 2, "strang", dt=2e-3)
+    pl, od = plan_and_oracle(sc, precision)
+    fp32 = precision == "fp32"
+    t, f = dev(sc.T0, fp32), dev(sc.fuel0, fp32)
+    pl.autotune(t, f, reps=3)
+    assert torch.equal(t, dev(sc.T0, fp32))           # autotune only reads the state
+    sched = [pl.schedule(0), pl.schedule(1)]
+    assert all(s["waves"] in (1, 2, 4, 8, 16) for s in sched)
+    assert 0 < sched[0]["table_rows"] < 80            # interior rows merged
+    T, F = oracle.step(od, host(t), host(f))
+    pl.step(t, f)
+    assert rel(host(t), T) < tol and rel(host(f), F) < tol
