@@ -168,18 +168,22 @@ iga_status iga_step(iga_plan *plan, void *T, void *fuel, void *stream);
  * IGA_ENONFINITE is returned at the first failure (state left as computed). */
 iga_status iga_run(iga_plan *plan, void *T, void *fuel, int64_t nsteps, void *stream);
 
-/* Line-solve schedule of direction dir: wavefronts (= lines) per workgroup,
- * rows per lane m (each line is split into 64 chunks of m rows), the compiled
- * register capacity used for m, and the largest compressed coefficient table
- * (rows kept per operator after merging the identical interior rows).  Any
- * output pointer may be NULL. */
-iga_status iga_plan_schedule(const iga_plan *plan, int32_t dir, int32_t *waves, int32_t *m,
-                             int32_t *capacity, int32_t *table_rows);
+/* Line-solve schedule of direction dir: lines per workgroup, wavefronts per
+ * line, rows per lane (each line is split into 64 * waves_per_line chunks of
+ * that many rows) and the largest compressed coefficient table (rows kept per
+ * operator after merging the identical interior rows).  Any output pointer
+ * may be NULL. */
+iga_status iga_plan_schedule(const iga_plan *plan, int32_t dir, int32_t *lines,
+                             int32_t *waves_per_line, int32_t *rows_per_lane,
+                             int32_t *table_rows);
 
-/* Choose the number of lines per workgroup for direction dir: waves in
- * {1, 2, 4, 8, 16}.  IGA_EUNSUPPORTED if the workgroup does not fit the
- * register or LDS budget for this line length. */
-iga_status iga_plan_set_schedule(iga_plan *plan, int32_t dir, int32_t waves);
+/* Choose the line-solve schedule of direction dir: lines in {1, 2, 4, 8, 16}
+ * lines per workgroup, waves_per_line in {1, 2, 4, 8} (0: the fewest that fit
+ * the register budget), lines * waves_per_line <= 16.  IGA_EUNSUPPORTED if the
+ * schedule does not fit the register or LDS budget for this line length; the
+ * previous schedule is kept. */
+iga_status iga_plan_set_schedule(iga_plan *plan, int32_t dir, int32_t lines,
+                                 int32_t waves_per_line);
 
 /* Assembly schedule: element rows marched per wavefront (>= 1). */
 iga_status iga_plan_set_assembly_rows(iga_plan *plan, int32_t rows);

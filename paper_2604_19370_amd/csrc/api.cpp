@@ -206,7 +206,7 @@ iga_status iga_plan_create(const iga_plan_desc *desc, iga_plan **out)
     try {
         pl->d = *desc;
         if ((st = build_plan_host(pl)) || (st = upload_plan(pl)) ||
-            (st = choose_schedule(pl, 0, 0)) || (st = choose_schedule(pl, 1, 0))) {
+            (st = choose_schedule(pl, 0, 0, 0)) || (st = choose_schedule(pl, 1, 0, 0))) {
             delete pl;
             return st;
         }
@@ -244,8 +244,8 @@ iga_status iga_factor_1d(iga_plan *plan, void *stream)
     if (st) return st;
     // the tables are known now: make sure each schedule still fits LDS
     for (int dir = 0; dir < 2; ++dir)
-        if (sweep_lds_bytes(plan, dir, plan->sched[dir].waves) > 160 * 1024)
-            if ((st = choose_schedule(plan, dir, 0))) return st;
+        if (sweep_lds_bytes(plan, dir, plan->sched[dir].lines, plan->sched[dir].wpl) > 160 * 1024)
+            if ((st = choose_schedule(plan, dir, 0, plan->sched[dir].wpl))) return st;
     plan->factored = true;
     plan->graph.reset();
     return IGA_OK;
@@ -331,15 +331,15 @@ iga_status iga_run(iga_plan *plan, void *T, void *fuel, int64_t nsteps, void *st
     return IGA_OK;
 }
 
-iga_status iga_plan_schedule(const iga_plan *plan, int32_t dir, int32_t *waves, int32_t *m,
-                             int32_t *capacity, int32_t *table_rows)
+iga_status iga_plan_schedule(const iga_plan *plan, int32_t dir, int32_t *lines,
+                             int32_t *waves_per_line, int32_t *rows_per_lane, int32_t *table_rows)
 {
     if (!plan) return fail(IGA_EINVAL, "plan is NULL");
     if (dir != 0 && dir != 1) return fail(IGA_EINVAL, "dir must be 0 or 1");
     const Schedule &sc = plan->sched[dir];
-    if (waves) *waves = sc.waves;
-    if (m) *m = sc.m;
-    if (capacity) *capacity = sc.mm;
+    if (lines) *lines = sc.lines;
+    if (waves_per_line) *waves_per_line = sc.wpl;
+    if (rows_per_lane) *rows_per_lane = sc.mm;
     if (table_rows) {
         int r = 0;
         for (int op = 0; op < NOPS; ++op)
@@ -349,15 +349,21 @@ iga_status iga_plan_schedule(const iga_plan *plan, int32_t dir, int32_t *waves, 
     return IGA_OK;
 }
 
-iga_status iga_plan_set_schedule(iga_plan *plan, int32_t dir, int32_t waves)
+iga_status iga_plan_set_schedule(iga_plan *plan, int32_t dir, int32_t lines, int32_t waves_per_line)
 {
     if (!plan) return fail(IGA_EINVAL, "plan is NULL");
     if (dir != 0 && dir != 1) return fail(IGA_EINVAL, "dir must be 0 or 1");
-    if (waves != 1 && waves != 2 && waves != 4 && waves != 8 && waves != 16)
-        return fail(IGA_EINVAL, "waves must be 1, 2, 4, 8 or 16");
+    auto pow2 = [](int v) { return v == 1 || v == 2 || v == 4 || v == 8 || v == 16; };
+    if (!pow2(lines)) return fail(IGA_EINVAL, "lines must be 1, 2, 4, 8 or 16");
+    if (waves_per_line != 0 && (!pow2(waves_per_line) || waves_per_line > 8))
+        return fail(IGA_EINVAL, "waves_per_line must be 0 (automatic), 1, 2, 4 or 8");
     Schedule old = plan->sched[dir];
-    iga_status st = choose_schedule(plan, dir, waves);
+    iga_status st = choose_schedule(plan, dir, lines, waves_per_line);
     if (st) {
+        if (plan->sched[dir].wpl != old.wpl || plan->sched[dir].mm != old.mm) {
+            plan->sched[dir] = old;
+            (void)build_scan_tables(plan, dir);
+        }
         plan->sched[dir] = old;
         return st;
     }
@@ -418,16 +424,20 @@ iga_status iga_autotune(iga_plan *plan, const void *T, const void *fuel, int32_t
             jobs[0] = SweepJob{R, out.ptr, OP_MY, -1, -1, bT, 0};
             nj = 1;
         }
-        Schedule keep = plan->sched[dir];
-        int best = keep.waves;
+        const Schedule keep = plan->sched[dir];
+        Schedule best = keep;
         float best_ms = 1e30f;
-        for (int w : {1, 2, 4, 8, 16}) {
-            if (choose_schedule(plan, dir, w) != IGA_OK) continue;
-            float ms = time_launches(s, reps, [&] { return launch_sweep(plan, dir, jobs, nj, s); });
-            if (ms >= 0 && ms < best_ms) { best_ms = ms; best = w; }
+        const int wmin = keep.wpl;
+        for (int wpl : {wmin, 2 * wmin, 4 * wmin}) {
+            if (wpl > 8) continue;
+            for (int w : {1, 2, 4, 8, 16}) {
+                if (w * wpl > 16) continue;
+                if (choose_schedule(plan, dir, w, wpl) != IGA_OK) continue;
+                float ms = time_launches(s, reps, [&] { return launch_sweep(plan, dir, jobs, nj, s); });
+                if (ms >= 0 && ms < best_ms) { best_ms = ms; best = plan->sched[dir]; }
+            }
         }
-        plan->sched[dir] = keep;
-        if ((st = choose_schedule(plan, dir, best))) return st;
+        if ((st = choose_schedule(plan, dir, best.lines, best.wpl))) return st;
     }
     IGA_HIP(hipStreamSynchronize(s));
     plan->graph.reset();

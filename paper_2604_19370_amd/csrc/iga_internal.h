@@ -58,11 +58,11 @@ enum BandId { BAND_BX = 0, BAND_BY = 1, NBANDS = 2 };
 
 inline int op_dir(int op) { return (op == OP_AX || op == OP_MX) ? 0 : 1; }
 
-// Schedule of the line solves in one direction: a workgroup of `waves`
-// wavefronts owns `waves` lines, one per wavefront; each lane holds a chunk of
-// m consecutive rows (64 chunks per line) in a register array of capacity mm.
+// Schedule of the line solves in one direction: a workgroup owns `lines`
+// lines, each worked by `wpl` wavefronts; each lane holds a chunk of mm
+// consecutive rows (64*wpl chunks per line, lines padded to 64*wpl*mm rows).
 struct Schedule {
-    int waves = 4, mm = 17, m = 0;
+    int lines = 4, wpl = 1, mm = 17;
 };
 
 // Compressed coefficient tables of one banded operator (host copy).  Rows
@@ -71,7 +71,7 @@ struct Schedule {
 //   rows[i*RS + j]      j < P: L(r, r-1-j);  rows[i*RS + P] = 1/U(r,r);
 //                       rows[i*RS + P + 1 + j] = U(r, r+1+j)/U(r,r)
 //   a64[i*RS + j]       A(r, r-P+j), j <= 2P (the operator, for refinement)
-//   tf[c*P*P]           forward transfer matrix of chunk c
+//   tf[c*P*P]           forward transfer matrix of chunk c (64*wpl chunks of mm rows)
 //   tb[c*P*P]           backward transfer matrix of chunk c
 struct OpHost {
     int K0 = 0, NK = 0, nrows = 0;
@@ -147,8 +147,9 @@ namespace iga {
 // host side (plan.cpp)
 iga_status build_plan_host(iga_plan *pl);
 iga_status upload_plan(iga_plan *pl);
-iga_status choose_schedule(iga_plan *pl, int dir, int waves);
+iga_status choose_schedule(iga_plan *pl, int dir, int lines, int wpl);
 iga_status build_solve_tables(iga_plan *pl);
+iga_status build_scan_tables(iga_plan *pl, int dir);
 
 // kernels (factor.hip)
 iga_status launch_factor(iga_plan *pl, hipStream_t s);
@@ -171,7 +172,7 @@ iga_status launch_sweep(const iga_plan *pl, int dir, const SweepJob *jobs, int n
                         hipStream_t s);
 int sweep_capacity(int m);           // smallest compiled register capacity >= m (0: none)
 iga_status sweep_prepare(const iga_plan *pl, int dir);
-size_t sweep_lds_bytes(const iga_plan *pl, int dir, int waves);
+size_t sweep_lds_bytes(const iga_plan *pl, int dir, int lines, int wpl);
 
 // kernels (util)
 iga_status launch_nonfinite(const iga_plan *pl, const void *T, const void *fuel, int *flag,

@@ -287,9 +287,9 @@ static inline int row_of(int r, int K0, int NK, int nrows)
 // (products of the companion matrices of forward and backward substitution,
 // from the compressed rows the kernels use; rows past N are the identity
 // padding rows).  The line-solve kernels compose them along their scan.
-static void scan_tables(OpHost &o, int N, int P, int m)
+static void scan_tables(OpHost &o, int N, int P, int m, int C)
 {
-    const int RS = 2 * P + 2, PP = P * P, C = 64, D = 6;
+    const int RS = 2 * P + 2, PP = P * P;
     std::vector<double> F((size_t)C * PP), B((size_t)C * PP);
     for (int c = 0; c < C; ++c) {
         std::vector<double> f(PP, 0.0), b(PP, 0.0);
@@ -325,7 +325,23 @@ static void scan_tables(OpHost &o, int N, int P, int m)
     }
     o.tf = F;
     o.tb = B;
-    (void)D;
+}
+
+// chunk transfer matrices of the current schedule of direction dir
+iga_status build_scan_tables(iga_plan *pl, int dir)
+{
+    const Schedule &sc = pl->sched[dir];
+    const int N = dir ? pl->Ny : pl->Nx;
+    iga_status st;
+    for (int op = 0; op < NOPS; ++op) {
+        if (op_dir(op) != dir) continue;
+        OpHost &o = pl->op_host[op];
+        if (o.rows.empty()) continue;   // not factored yet
+        scan_tables(o, N, pl->P, sc.mm, 64 * sc.wpl);
+        if ((st = upload_state(pl, pl->op_tf[op], o.tf))) return st;
+        if ((st = upload_state(pl, pl->op_tb[op], o.tb))) return st;
+    }
+    return IGA_OK;
 }
 
 iga_status build_solve_tables(iga_plan *pl)
@@ -363,12 +379,11 @@ iga_status build_solve_tables(iga_plan *pl)
         id[P] = 1.0;
         o.a64.insert(o.a64.end(), id.begin(), id.end());
         o.nrows = (int)(o.rows.size() / RS);
-        scan_tables(o, N, P, pl->sched[dir].m);
         if ((st = upload_state(pl, pl->op_rows[op], o.rows))) return st;
         if ((st = upload_vec<double>(pl->op_a64c[op], o.a64))) return st;
-        if ((st = upload_state(pl, pl->op_tf[op], o.tf))) return st;
-        if ((st = upload_state(pl, pl->op_tb[op], o.tb))) return st;
     }
+    for (int dir = 0; dir < 2; ++dir)
+        if ((st = build_scan_tables(pl, dir))) return st;
     for (int b = 0; b < NBANDS; ++b) {
         const int N = b == BAND_BX ? pl->Nx : pl->Ny;
         std::vector<double> a((size_t)N * RS, 0.0);
@@ -388,36 +403,49 @@ iga_status build_solve_tables(iga_plan *pl)
 // ---------------------------------------------------------------------------
 // line-solve schedules
 // ---------------------------------------------------------------------------
-iga_status choose_schedule(iga_plan *pl, int dir, int waves)
+iga_status choose_schedule(iga_plan *pl, int dir, int lines, int wpl)
 {
     const int N = dir ? pl->Ny : pl->Nx, P = pl->P;
     const int nlines = dir ? pl->Nx : pl->Ny;
-    // each lane holds mm rows; the line is padded to 64 mm rows
-    const int mm = sweep_capacity(std::max((N + 63) / 64, P));
-    const int m = mm;
-    if (!mm) return fail(IGA_EUNSUPPORTED, "lines of " + std::to_string(N) + " dofs exceed the "
-                                           "compiled register capacity (at most 65 rows per lane)");
-    Schedule &sc = pl->sched[dir];
-    sc.mm = mm;
-    sc.m = m;
-    const int bound = mm <= 17 ? 16 : (mm <= 33 ? 8 : 4);
-    if (waves <= 0) {
-        // widest workgroup that fits LDS and still gives >= 256 workgroups
-        waves = 1;
-        for (int w : {16, 8, 4, 2}) {
-            if (w > bound || sweep_lds_bytes(pl, dir, w) > 160 * 1024) continue;
-            if ((nlines + w - 1) / w >= 256 || w == 2) { waves = w; break; }
-        }
-        if (dir == 0 && waves < 4 && bound >= 4 && sweep_lds_bytes(pl, dir, 4) <= 160 * 1024)
-            waves = 4;
+    // wavefronts per line: the fewest that keep a lane's chunk within the
+    // largest compiled register capacity
+    if (wpl <= 0) {
+        wpl = 1;
+        while (wpl < 8 && !sweep_capacity(std::max((N + 64 * wpl - 1) / (64 * wpl), P))) wpl *= 2;
     }
-    if (sweep_lds_bytes(pl, dir, waves) > 160 * 1024)
-        return fail(IGA_EUNSUPPORTED, "line-solve workgroup of " + std::to_string(waves) +
+    const int mm = sweep_capacity(std::max((N + 64 * wpl - 1) / (64 * wpl), P));
+    if (!mm) return fail(IGA_EUNSUPPORTED, "lines of " + std::to_string(N) + " dofs need more than "
+                                           "8 wavefronts per line");
+    Schedule &sc = pl->sched[dir];
+    const Schedule old = sc;
+    sc.mm = mm;
+    sc.wpl = wpl;
+    const int maxw = (!pl->fp32 && pl->P == 3 && mm >= 12) ? 8 : 16;   // wavefronts per workgroup
+    if (lines <= 0) {
+        // widest workgroup (<= 16 wavefronts) that fits LDS and still gives
+        // >= 256 workgroups; at least 4 lines for strided x-lines
+        lines = 1;
+        for (int w : {16, 8, 4, 2}) {
+            if (w * wpl > maxw || sweep_lds_bytes(pl, dir, w, wpl) > 160 * 1024) continue;
+            if ((nlines + w - 1) / w >= 256 || w == 2) { lines = w; break; }
+        }
+        if (dir == 0 && lines < 4 && 4 * wpl <= maxw && sweep_lds_bytes(pl, dir, 4, wpl) <= 160 * 1024)
+            lines = 4;
+    }
+    if (lines * wpl > maxw || (lines & (lines - 1)) || (wpl & (wpl - 1))) {
+        sc = old;
+        return fail(IGA_EUNSUPPORTED, "a workgroup holds at most " + std::to_string(maxw) +
+                                          " wavefronts (lines x waves per line) here");
+    }
+    if (sweep_lds_bytes(pl, dir, lines, wpl) > 160 * 1024) {
+        sc = old;
+        return fail(IGA_EUNSUPPORTED, "line-solve workgroup of " + std::to_string(lines) +
                                           " lines does not fit in LDS");
-    if (waves > bound)
-        return fail(IGA_EUNSUPPORTED, "at most " + std::to_string(bound) +
-                                          " lines per workgroup for this line length");
-    sc.waves = waves;
+    }
+    sc.lines = lines;
+    iga_status st;
+    if (old.wpl != sc.wpl || old.mm != sc.mm)
+        if ((st = build_scan_tables(pl, dir))) return st;
     return sweep_prepare(pl, dir);
 }
 

@@ -17,7 +17,7 @@ static SweepFn pick_fn(bool fp32, int P, int mm, bool diry)
 
 int sweep_capacity(int m)
 {
-    static const int caps[] = {4, 8, 12, 17, 33, 48, 65};
+    static const int caps[] = {4, 8, 12, 17};
     for (int c : caps)
         if (m <= c) return c;
     return 0;
@@ -27,16 +27,16 @@ static size_t align16(size_t b) { return (b + 15) & ~(size_t)15; }
 
 static size_t stage_stride(int N, int dir) { return dir ? (size_t)N : (size_t)(N | 1); }
 
-// LDS of one workgroup: the staged lines plus the largest table set a job of
-// this direction stages (two factored operators with their refinement rows and
-// scan tables, and one band).
-size_t sweep_lds_bytes(const iga_plan *pl, int dir, int waves)
+// LDS of one workgroup: the staged lines, the largest table set a job of this
+// direction stages (two factored operators with their refinement rows and
+// chunk transfer matrices, and one band) and the line exchange slots.
+size_t sweep_lds_bytes(const iga_plan *pl, int dir, int lines, int wpl)
 {
     const size_t w = pl->wsize;
     const int N = dir ? pl->Ny : pl->Nx;
-    const int P = pl->P, RS = 2 * P + 2;
-    const size_t scan = (size_t)64 * P * P * w;
-    size_t b = align16((size_t)waves * stage_stride(N, dir) * w);
+    const int P = pl->P, RS = 2 * P + 2, PP = P * P;
+    const size_t scan = (size_t)64 * wpl * PP * w;
+    size_t b = align16((size_t)lines * stage_stride(N, dir) * w);
     int maxrows = 0;
     for (int op = 0; op < NOPS; ++op)
         if (op_dir(op) == dir) maxrows = std::max(maxrows, pl->op_host[op].nrows);
@@ -46,6 +46,7 @@ size_t sweep_lds_bytes(const iga_plan *pl, int dir, int waves)
     const size_t op_bytes = align16((size_t)maxrows * RS * w) +
                             (pl->fp32 ? align16((size_t)maxrows * RS * 8) : 0) + 2 * align16(scan);
     b += 2 * op_bytes + align16((size_t)maxrows * RS * w);
+    b += align16((size_t)lines * 2 * wpl * (PP + P) * w) + align16((size_t)lines * 2 * wpl * 2 * P * w);
     return b;
 }
 
@@ -84,12 +85,13 @@ iga_status launch_sweep(const iga_plan *pl, int dir, const SweepJob *jobs, int n
     prm.N = dir ? pl->Ny : pl->Nx;
     prm.nlines = dir ? pl->Nx : pl->Ny;
     prm.ld = pl->Ny;
-    prm.m = sc.m;
     prm.Ns = (int)stage_stride(prm.N, dir);
-    const int nblk = (prm.nlines + sc.waves - 1) / sc.waves;
-    const size_t lds = sweep_lds_bytes(pl, dir, sc.waves);
+    prm.W = sc.lines;
+    prm.WPL = sc.wpl;
+    const int nblk = (prm.nlines + sc.lines - 1) / sc.lines;
+    const size_t lds = sweep_lds_bytes(pl, dir, sc.lines, sc.wpl);
     if (lds > 160 * 1024) return fail(IGA_EUNSUPPORTED, "line-solve tables do not fit in LDS");
-    hipLaunchKernelGGL(fn, dim3(nblk, njobs), dim3(sc.waves * 64), lds, s, prm);
+    hipLaunchKernelGGL(fn, dim3(nblk, njobs), dim3(sc.lines * sc.wpl * 64), lds, s, prm);
     IGA_HIP(hipGetLastError());
     return IGA_OK;
 }

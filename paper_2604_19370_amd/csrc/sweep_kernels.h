@@ -1,32 +1,28 @@
 // sweep_kernels.h -- batched banded line solves of the Kronecker-factored
 // systems (Section 4: N_y independent solves of size N_x for an x substep,
-// N_x of size N_y for a y substep), one wavefront per line.
+// N_x of size N_y for a y substep).
 //
-// A workgroup of W wavefronts owns W consecutive lines.  It stages them in LDS
-// with coalesced loads (rows of W consecutive columns for x-lines, W whole
-// contiguous rows for y-lines), and wavefront w solves line w: lane c holds
-// rows [c*m, c*m + m) of the line in registers (64 chunks per line).
+// A workgroup owns W consecutive lines and stages them in LDS with coalesced
+// loads (rows of W consecutive columns for x-lines, W whole contiguous rows
+// for y-lines).  Each line is worked by WPL wavefronts; lane c of the line
+// (c = part*64 + lane) holds rows [c*MM, c*MM + MM) in registers.  The line is
+// padded to 64*WPL*MM rows with identity rows (no multipliers, unit pivot,
+// zero data), which leaves the LU solve of the real rows unchanged and keeps
+// the recurrences free of per-row predication.
 //
 // Forward and backward substitution are linear recurrences with a p-vector
 // state, affine over a chunk: s_out = Phi_c s_in + psi_c(b).  Each lane runs
-// its chunk from a zero state, the 64 chunk end-states are combined by a
-// Hillis-Steele scan across the wavefront's lanes (shuffles, no barriers)
-// whose matrix parts -- products of the rows' companion matrices, which do not
-// depend on the data -- start from each chunk's precomputed transfer matrix and
-// are composed along the scan, and each lane re-runs its chunk from its exact
-// incoming state.  The result is the banded
-// LU solve of the whole line.
-//
-// Every lane holds exactly mm rows: a line of N rows is padded to 64*mm rows
-// with identity rows (no multipliers, unit pivot, zero data), which leaves the
-// LU solve of the real rows unchanged and keeps the recurrences free of
-// per-row predication.
+// its chunk from a zero state; the chunk maps (Phi_c, psi_c) are combined by a
+// Hillis-Steele scan across the wavefront's lanes (shuffles), composing the
+// precomputed per-chunk transfer matrices as it goes, then across the WPL
+// wavefronts of the line (one LDS exchange); each lane re-runs its chunk from
+// its exact incoming state.  The result is the banded LU solve of the line.
 //
 // Coefficients.  Interior rows of a factored operator on a uniform mesh agree
 // to rounding (the LU of a banded Toeplitz matrix converges to a constant row
-// within a few tens of rows); the plan keeps rows [0, K0) and [NK, N) as they
-// are and one canonical row for [K0, NK), in LDS, so lanes on interior chunks
-// all read the same address.
+// within a few tens of rows); the plan keeps rows [0, K0) and [NK, N), one
+// canonical row for [K0, NK) and an identity row for the padding, in LDS, so
+// lanes on interior chunks all read the same address.
 //
 // FP32 plans: every solve is x0 = LU32^{-1} b, r = b - A64 x0 formed in double,
 // x = x0 + LU32^{-1} r (one step of iterative refinement), and the state is
@@ -37,13 +33,13 @@
 namespace iga {
 
 constexpr int MAXJOBS = 4;
-constexpr int SCAN_LEVELS = 6;   // 64 chunks per line
+constexpr int MAXWPL = 8;        // wavefronts per line
 
 // compressed coefficient rows (device, state precision unless noted)
 struct OpTab {
     const void *rows;     // [nrows][RS] : L(r, r-1-j) j<P, 1/U(r,r), U(r,r+1+j)/U(r,r)
     const double *a64;    // [nrows][RS] : A(r, r-P .. r+P) in double
-    const void *tf, *tb;  // [64][P*P] forward / backward transfer matrix of each chunk
+    const void *tf, *tb;  // [64*WPL][P*P] forward / backward transfer matrix of each chunk
     int K0, NK, nrows;    // row r -> table row min(min(r, K0) + max(0, r - NK + 1), nrows - 1)
 };
 struct BandTab {
@@ -58,8 +54,9 @@ struct SweepParams {
     int N;        // line length
     int nlines;   // lines
     int ld;       // row stride of the field (Ny)
-    int m;        // rows per chunk
     int Ns;       // LDS stride between staged lines
+    int W;        // lines per workgroup (power of two)
+    int WPL;      // wavefronts per line (power of two)
 };
 
 template <int P> struct RowStride {
@@ -123,19 +120,30 @@ __device__ __forceinline__ void bwd(T (&x)[MM], int r0, const T *rows, const Row
     }
 }
 
-// Scan of the chunk end-states across the 64 lanes: a Hillis-Steele scan of
-// the affine chunk maps (Phi_c, psi_c), composing the matrices as it goes, so
-// only each chunk's own transfer matrix is needed.  On exit v is the state
-// entering this lane's chunk from the left (FWD) or from the right.
+// Per-line context of a wavefront: which part of the line it works and the
+// LDS slots shared by the line's wavefronts.
+template <typename T> struct LineCtx {
+    int lane, part, WPL;
+    T *xscan;   // [2][WPL][P*P + P] wave totals of the two alternating scans
+    T *xnb;     // [2][WPL][2P] first / last P values of each wavefront's rows
+    int flip, nflip;
+};
+
+// Scan of the chunk maps along the line; on entry v is this chunk's
+// particular end-state (zero incoming state), on exit the exact state
+// entering this chunk from the left (FWD) or from the right.
 template <typename T, int P, bool FWD>
-__device__ __forceinline__ void wave_scan(T (&v)[P], int lane, const T *__restrict__ tab)
+__device__ __forceinline__ void line_scan(T (&v)[P], const T *__restrict__ tab, LineCtx<T> &ctx)
 {
     constexpr int PP = P * P;
+    const int lane = ctx.lane;
     T F[PP];
+    const int c = ctx.part * 64 + lane;
 #pragma unroll
-    for (int i = 0; i < PP; ++i) F[i] = tab[lane * PP + i];
+    for (int i = 0; i < PP; ++i) F[i] = tab[c * PP + i];
+    // inclusive scan within the wavefront
 #pragma unroll
-    for (int d = 0; d < SCAN_LEVELS; ++d) {
+    for (int d = 0; d < 6; ++d) {
         const int off = 1 << d;
         T o[P], oF[PP];
 #pragma unroll
@@ -143,61 +151,149 @@ __device__ __forceinline__ void wave_scan(T (&v)[P], int lane, const T *__restri
 #pragma unroll
         for (int i = 0; i < PP; ++i) oF[i] = FWD ? shfl_up(F[i], off) : shfl_down(F[i], off);
         const bool has = FWD ? lane >= off : lane + off < 64;
-        if (has) {
-            T nF[PP];
+        T nF[PP], nv[P];
 #pragma unroll
-            for (int i = 0; i < P; ++i) {
+        for (int i = 0; i < P; ++i) {
+            nv[i] = v[i];
 #pragma unroll
-                for (int j = 0; j < P; ++j) {
-                    v[i] += F[i * P + j] * o[j];
-                    T s = T(0);
+            for (int j = 0; j < P; ++j) {
+                nv[i] += F[i * P + j] * o[j];
+                T s = T(0);
 #pragma unroll
-                    for (int k = 0; k < P; ++k) s += F[i * P + k] * oF[k * P + j];
-                    nF[i * P + j] = s;
-                }
+                for (int k = 0; k < P; ++k) s += F[i * P + k] * oF[k * P + j];
+                nF[i * P + j] = s;
             }
-#pragma unroll
-            for (int i = 0; i < PP; ++i) F[i] = nF[i];
         }
+#pragma unroll
+        for (int i = 0; i < P; ++i) v[i] = has ? nv[i] : v[i];
+#pragma unroll
+        for (int i = 0; i < PP; ++i) F[i] = has ? nF[i] : F[i];
     }
+    // exclusive maps: shift by one lane (identity map at the wave's first lane)
+    const int edge = FWD ? 0 : 63;
+    T ev[P];
 #pragma unroll
     for (int j = 0; j < P; ++j) {
         const T o = FWD ? shfl_up(v[j], 1) : shfl_down(v[j], 1);
-        v[j] = (FWD ? lane > 0 : lane < 63) ? o : T(0);
+        ev[j] = lane == edge ? T(0) : o;
+    }
+    if (ctx.WPL == 1) {
+#pragma unroll
+        for (int j = 0; j < P; ++j) v[j] = ev[j];
+        return;
+    }
+    T eF[PP];
+#pragma unroll
+    for (int i = 0; i < PP; ++i) {
+        const T o = FWD ? shfl_up(F[i], 1) : shfl_down(F[i], 1);
+        eF[i] = lane == edge ? ((i / P == i % P) ? T(1) : T(0)) : o;
+    }
+    // wave totals across the line's wavefronts (two alternating slot sets, so
+    // one barrier per scan suffices)
+    constexpr int SL = PP + P;
+    T *slot = ctx.xscan + (size_t)ctx.flip * ctx.WPL * SL;
+    ctx.flip ^= 1;
+    const int last = FWD ? 63 : 0;
+    if (lane == last) {
+        T *me = slot + ctx.part * SL;
+#pragma unroll
+        for (int i = 0; i < PP; ++i) me[i] = F[i];
+#pragma unroll
+        for (int j = 0; j < P; ++j) me[PP + j] = v[j];
+    }
+    __syncthreads();
+    T S[P];
+#pragma unroll
+    for (int j = 0; j < P; ++j) S[j] = T(0);
+    const int q0 = FWD ? 0 : ctx.WPL - 1;
+    const int nq = FWD ? ctx.part : ctx.WPL - 1 - ctx.part;
+    for (int t = 0; t < nq; ++t) {
+        const int q = FWD ? q0 + t : q0 - t;
+        const T *o = slot + q * SL;
+        T n[P];
+#pragma unroll
+        for (int i = 0; i < P; ++i) {
+            n[i] = o[PP + i];
+#pragma unroll
+            for (int j = 0; j < P; ++j) n[i] += o[i * P + j] * S[j];
+        }
+#pragma unroll
+        for (int i = 0; i < P; ++i) S[i] = n[i];
+    }
+#pragma unroll
+    for (int i = 0; i < P; ++i) {
+        T s = ev[i];
+#pragma unroll
+        for (int j = 0; j < P; ++j) s += eF[i * P + j] * S[j];
+        v[i] = s;
     }
 }
 
 template <typename T, int P, int MM>
 __device__ __forceinline__ void chunk_solve(T (&x)[MM], const T *rows, const T *tf, const T *tb,
-                                            const RowMap &rm, int lane, int r0)
+                                            const RowMap &rm, LineCtx<T> &ctx, int r0)
 {
     T s[P];
 #pragma unroll
     for (int j = 0; j < P; ++j) s[j] = T(0);
     fwd<T, P, MM, false>(x, r0, rows, rm, s);
-    wave_scan<T, P, true>(s, lane, tf);
+    line_scan<T, P, true>(s, tf, ctx);
     fwd<T, P, MM, true>(x, r0, rows, rm, s);
 #pragma unroll
     for (int j = 0; j < P; ++j) s[j] = T(0);
     bwd<T, P, MM, false>(x, r0, rows, rm, s);
-    wave_scan<T, P, false>(s, lane, tb);
+    line_scan<T, P, false>(s, tb, ctx);
     bwd<T, P, MM, true>(x, r0, rows, rm, s);
 }
 
-// Values of the line at rows r0-P .. r0+MM+P-1 as seen from this chunk:
-// xe[P + k] = x[k], the neighbouring chunks' values beyond.
+// The P rows of the line just before (left) and just after (right) this
+// lane's chunk.
 template <typename T, int P, int MM>
-__device__ __forceinline__ void neighbours(const T (&x)[MM], T (&xe)[MM + 2 * P], int lane)
+__device__ __forceinline__ void neighbours(const T (&x)[MM], T (&left)[P], T (&right)[P],
+                                           LineCtx<T> &ctx)
 {
+    const int lane = ctx.lane;
 #pragma unroll
     for (int i = 0; i < P; ++i) {
-        const T left = shfl_up(x[MM - P + i], 1);
-        const T right = shfl_down(x[i], 1);
-        xe[i] = lane > 0 ? left : T(0);
-        xe[P + MM + i] = lane < 63 ? right : T(0);
+        left[i] = shfl_up(x[MM - P + i], 1);
+        right[i] = shfl_down(x[i], 1);
     }
+    if (ctx.WPL == 1) {
 #pragma unroll
-    for (int k = 0; k < MM; ++k) xe[P + k] = x[k];
+        for (int i = 0; i < P; ++i) {
+            left[i] = lane > 0 ? left[i] : T(0);
+            right[i] = lane < 63 ? right[i] : T(0);
+        }
+        return;
+    }
+    // across the line's wavefronts: lanes 0 and 63 publish their edge rows
+    T *nb = ctx.xnb + (size_t)ctx.nflip * ctx.WPL * 2 * P;
+    ctx.nflip ^= 1;
+    T *me = nb + ctx.part * 2 * P;
+    if (lane == 0) {
+#pragma unroll
+        for (int i = 0; i < P; ++i) me[i] = x[i];
+    }
+    if (lane == 63) {
+#pragma unroll
+        for (int i = 0; i < P; ++i) me[P + i] = x[MM - P + i];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < P; ++i) {
+        const T l = ctx.part > 0 ? nb[(ctx.part - 1) * 2 * P + P + i] : T(0);
+        const T r = ctx.part + 1 < ctx.WPL ? nb[(ctx.part + 1) * 2 * P + i] : T(0);
+        left[i] = lane > 0 ? left[i] : l;
+        right[i] = lane < 63 ? right[i] : r;
+    }
+}
+
+// value of the line at chunk-relative row idx (compile-time), P <= MM
+template <typename T, int P, int MM>
+__device__ __forceinline__ T around(const T (&x)[MM], const T (&left)[P], const T (&right)[P],
+                                    int idx)
+{
+    return idx < 0 ? left[idx + P] : (idx >= MM ? right[idx - MM] : x[idx]);
 }
 
 // One operator's tables as the kernel sees them (rows in LDS).
@@ -208,28 +304,32 @@ template <typename T> struct OpView {
     RowMap rm;
 };
 
+// x <- A^{-1} x; FP32 refines once with the residual b - A64 x0 in double
+// (b = the value of x on entry).
 template <typename T, int P, int MM>
-__device__ __forceinline__ void solve_refined(T (&x)[MM], const OpView<T> &op, int lane, int r0)
+__device__ __forceinline__ void solve_refined(T (&x)[MM], const OpView<T> &op, LineCtx<T> &ctx,
+                                              int r0)
 {
     if constexpr (sizeof(T) == 8) {
-        chunk_solve<T, P, MM>(x, op.rows, op.tf, op.tb, op.rm, lane, r0);
+        chunk_solve<T, P, MM>(x, op.rows, op.tf, op.tb, op.rm, ctx, r0);
     } else {
         constexpr int RS = RowStride<P>::RS;
         T b[MM];
 #pragma unroll
         for (int k = 0; k < MM; ++k) b[k] = x[k];
-        chunk_solve<T, P, MM>(x, op.rows, op.tf, op.tb, op.rm, lane, r0);
-        T xe[MM + 2 * P];
-        neighbours<T, P, MM>(x, xe, lane);
+        chunk_solve<T, P, MM>(x, op.rows, op.tf, op.tb, op.rm, ctx, r0);
+        T left[P], right[P];
+        neighbours<T, P, MM>(x, left, right, ctx);
 #pragma unroll
         for (int k = 0; k < MM; ++k) {
             const double *a = op.a64 + row_index(r0 + k, op.rm) * RS;
             double r = (double)b[k];
 #pragma unroll
-            for (int j = 0; j < 2 * P + 1; ++j) r -= a[j] * (double)xe[k + j];
+            for (int j = 0; j < 2 * P + 1; ++j)
+                r -= a[j] * (double)around<T, P, MM>(x, left, right, k + j - P);
             b[k] = (T)r;
         }
-        chunk_solve<T, P, MM>(b, op.rows, op.tf, op.tb, op.rm, lane, r0);
+        chunk_solve<T, P, MM>(b, op.rows, op.tf, op.tb, op.rm, ctx, r0);
 #pragma unroll
         for (int k = 0; k < MM; ++k) x[k] += b[k];
     }
@@ -256,31 +356,36 @@ __device__ __forceinline__ void stage_table(U *dst, const void *src, int n)
     }
 }
 
-template <int MM> struct SweepBounds {
-    static constexpr int value = MM <= 17 ? 1024 : (MM <= 33 ? 512 : 256);
-};
+// workgroup size bound: 16 wavefronts, or 8 where cubic double chunks of 12+
+// rows need more than 128 registers
+template <typename T, int P, int MM> constexpr int sweep_max_threads()
+{
+    return (sizeof(T) == 8 && P == 3 && MM >= 12) ? 512 : 1024;
+}
 
 template <typename T, int P, int MM, bool DIRY>
-__global__ __launch_bounds__(SweepBounds<MM>::value) void k_sweep(SweepParams prm)
+__global__ __launch_bounds__((sweep_max_threads<T, P, MM>())) void k_sweep(SweepParams prm)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     constexpr int RS = RowStride<P>::RS;
-    constexpr int SCAN = 64 * P * P;                  // chunk transfer matrices per direction
+    constexpr int PP = P * P;
     constexpr bool F32 = sizeof(T) == 4;
     const SweepJob job = prm.jobs[blockIdx.y];
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-    const int W = blockDim.x >> 6;            // lines per workgroup (power of two)
+    const int W = prm.W, WPL = prm.WPL;
     const int wlog = __builtin_ctz(W);
     const int rstep = blockDim.x >> wlog;
     const int N = prm.N, Ns = prm.Ns, ld = prm.ld;
     const int blk = xcd_remap(blockIdx.x, gridDim.x);
     const int line0 = blk * W;
     const int nl = min(W, prm.nlines - line0);
+    const int lw = wave / WPL;          // line of this wavefront within the workgroup
+    const int part = wave - lw * WPL;   // its part of the line
+    const int C = 64 * WPL;             // chunks per line
 
-    // LDS: staged lines, then the tables of this job (coefficient rows, the
-    // refinement operator rows, the chunk scan tables, the explicit band)
+    // LDS: staged lines, then the tables of this job and the line exchange slots
     T *st = reinterpret_cast<T *>(smem);
     size_t off = ((size_t)W * Ns * sizeof(T) + 15) & ~(size_t)15;
     auto take = [&](size_t bytes) {
@@ -298,10 +403,10 @@ __global__ __launch_bounds__(SweepBounds<MM>::value) void k_sweep(SweepParams pr
             stage_table<double>(a, t.a64, t.nrows * RS);
             v.a64 = a;
         }
-        T *tf = reinterpret_cast<T *>(take((size_t)SCAN * sizeof(T)));
-        T *tb = reinterpret_cast<T *>(take((size_t)SCAN * sizeof(T)));
-        stage_table<T>(tf, t.tf, SCAN);
-        stage_table<T>(tb, t.tb, SCAN);
+        T *tf = reinterpret_cast<T *>(take((size_t)C * PP * sizeof(T)));
+        T *tb = reinterpret_cast<T *>(take((size_t)C * PP * sizeof(T)));
+        stage_table<T>(tf, t.tf, C * PP);
+        stage_table<T>(tb, t.tb, C * PP);
         v.tf = tf;
         v.tb = tb;
         v.rm = RowMap{t.K0, t.NK - 1, t.nrows - 1};
@@ -319,6 +424,16 @@ __global__ __launch_bounds__(SweepBounds<MM>::value) void k_sweep(SweepParams pr
         brow = rows;
         brm = RowMap{t.K0, t.NK - 1, t.nrows - 1};
     }
+    LineCtx<T> ctx;
+    ctx.lane = lane;
+    ctx.part = part;
+    ctx.WPL = WPL;
+    ctx.flip = 0;
+    ctx.nflip = 0;
+    ctx.xscan = reinterpret_cast<T *>(take((size_t)W * 2 * WPL * (PP + P) * sizeof(T))) +
+                (size_t)lw * 2 * WPL * (PP + P);
+    ctx.xnb = reinterpret_cast<T *>(take((size_t)W * 2 * WPL * 2 * P * sizeof(T))) +
+              (size_t)lw * 2 * WPL * 2 * P;
 
     // Stage W lines of a field (src layout) into st, and back.  Loads are
     // issued in batches of UNR per thread before their LDS stores so that
@@ -377,39 +492,38 @@ __global__ __launch_bounds__(SweepBounds<MM>::value) void k_sweep(SweepParams pr
     load_lines(static_cast<const T *>(job.src));
     __syncthreads();
 
-    // lane's chunk: rows [r0, r0 + MM) of line `wave`; rows >= N are padding
-    const int r0 = lane * MM;
-    const bool live = wave < nl;
-    const T *mine = st + wave * Ns;
+    // this lane's chunk: rows [r0, r0 + MM) of line lw; rows >= N are padding
+    const int r0 = (part * 64 + lane) * MM;
+    const bool live = lw < nl;
+    T *mine = st + lw * Ns + r0;   // valid for rows r0 + k < N
     T x[MM];
 #pragma unroll
-    for (int k = 0; k < MM; ++k) x[k] = (live && r0 + k < N) ? mine[r0 + k] : T(0);
-    __syncthreads();
+    for (int k = 0; k < MM; ++k) x[k] = (live && r0 + k < N) ? mine[k] : T(0);
 
-    if (has0) solve_refined<T, P, MM>(x, v0, lane, r0);
+    if (has0) solve_refined<T, P, MM>(x, v0, ctx, r0);
     if (job.base) {
         // increment form: the solve produced x - base; add the base state
+        __syncthreads();
         load_lines(static_cast<const T *>(job.base));
         __syncthreads();
 #pragma unroll
         for (int k = 0; k < MM; ++k)
-            if (live && r0 + k < N) x[k] += mine[r0 + k];
-        __syncthreads();
+            if (live && r0 + k < N) x[k] += mine[k];
     }
     if (hasb) {
         // explicit Crank-Nicolson operator along the line, then the second solve
-        T xe[MM + 2 * P];
-        neighbours<T, P, MM>(x, xe, lane);
+        T left[P], right[P];
+        neighbours<T, P, MM>(x, left, right, ctx);
         T y[MM];
 #pragma unroll
         for (int k = 0; k < MM; ++k) {
             const T *a = brow + row_index(r0 + k, brm) * RS;
             T v = T(0);
 #pragma unroll
-            for (int j = 0; j < 2 * P + 1; ++j) v += a[j] * xe[k + j];
+            for (int j = 0; j < 2 * P + 1; ++j) v += a[j] * around<T, P, MM>(x, left, right, k + j - P);
             y[k] = v;
         }
-        if (has1) solve_refined<T, P, MM>(y, v1, lane, r0);
+        if (has1) solve_refined<T, P, MM>(y, v1, ctx, r0);
         if (job.add_after) {
 #pragma unroll
             for (int k = 0; k < MM; ++k) x[k] += y[k];
@@ -419,16 +533,19 @@ __global__ __launch_bounds__(SweepBounds<MM>::value) void k_sweep(SweepParams pr
         }
     }
 
+    __syncthreads();
+    if (live) {
 #pragma unroll
-    for (int k = 0; k < MM; ++k)
-        if (live && r0 + k < N) st[wave * Ns + r0 + k] = x[k];
+        for (int k = 0; k < MM; ++k)
+            if (r0 + k < N) mine[k] = x[k];
+    }
     __syncthreads();
     store_lines(static_cast<T *>(job.dst));
 }
 
 using SweepFn = void (*)(SweepParams);
 
-#define IGA_SWEEP_MMS(X) X(4) X(8) X(12) X(17) X(33) X(48) X(65)
+#define IGA_SWEEP_MMS(X) X(4) X(8) X(12) X(17)
 
 template <typename T, int P> static SweepFn pick_mm(int mm, bool diry)
 {

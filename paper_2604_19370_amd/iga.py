@@ -76,7 +76,7 @@ def lib() -> ctypes.CDLL:
         L.iga_step.argtypes = [vp, vp, vp, vp]
         L.iga_run.argtypes = [vp, vp, vp, i64, vp]
         L.iga_plan_schedule.argtypes = [vp, i32] + [ctypes.POINTER(i32)] * 4
-        L.iga_plan_set_schedule.argtypes = [vp, i32, i32]
+        L.iga_plan_set_schedule.argtypes = [vp, i32, i32, i32]
         L.iga_plan_set_assembly_rows.argtypes = [vp, i32]
         L.iga_plan_assembly_rows.argtypes = [vp]
         L.iga_plan_assembly_rows.restype = i32
@@ -214,7 +214,8 @@ class Plan:
         v = [ctypes.c_int32() for _ in range(4)]
         _check(lib().iga_plan_schedule(self._h, int(dir), *[ctypes.byref(x) for x in v]),
                "iga_plan_schedule")
-        return dict(waves=v[0].value, m=v[1].value, capacity=v[2].value, table_rows=v[3].value)
+        return dict(lines=v[0].value, waves_per_line=v[1].value, rows_per_lane=v[2].value,
+                    table_rows=v[3].value)
 
     @property
     def assembly_rows(self) -> int:
@@ -224,8 +225,9 @@ class Plan:
         _check(lib().iga_autotune(self._h, self._field(T, "T"), self._field(fuel, "fuel"),
                                   int(reps), _stream(stream)), "iga_autotune")
 
-    def set_schedule(self, dir, waves):
-        _check(lib().iga_plan_set_schedule(self._h, int(dir), int(waves)), "iga_plan_set_schedule")
+    def set_schedule(self, dir, lines, waves_per_line=0):
+        _check(lib().iga_plan_set_schedule(self._h, int(dir), int(lines), int(waves_per_line)),
+               "iga_plan_set_schedule")
 
     def set_assembly_rows(self, rows):
         _check(lib().iga_plan_set_assembly_rows(self._h, int(rows)), "iga_plan_set_assembly_rows")
