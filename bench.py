@@ -38,6 +38,11 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--kernel-reps", type=int, default=50)
+    ap.add_argument("--kernels-only", action="store_true",
+                    help="only launch each kernel of the FP32 step --kernel-reps times, plus a "
+                         "copy kernel of known size (for profiler runs)")
+    ap.add_argument("--schedule", type=str, default=None,
+                    help="fixed schedule 'xlines,xwpl,ylines,ywpl,asmrows' instead of autotuning")
     return ap.parse_args()
 
 
@@ -103,6 +108,95 @@ def kernel_times(pl, sc, reps, torch):
     return out
 
 
+# Algorithmic work per unit (p = 2, FP32 plan).  Assembly: flops per element of
+# the sum-factorised quadrature (row reuse along the marching direction) plus the
+# pointwise terms; sweeps and the assembly's memory side: bytes per dof.
+def assembly_flops(p, fuel):
+    n = q = p + 1
+    fma = 2 * q * n + 3 * q * q * n          # T, dT/dx, dT/dy at the points
+    fma += 3 * n * q * q + 2 * n * n * q     # test contraction (v, dv/dx, dv/dy)
+    if fuel:
+        fma += q * n + q * q * n             # fuel at the points (also read by S3's indicator)
+        fma += n * q * q + n * n * q         # fuel right-hand side
+    else:
+        fma += q * n + q * q * n
+    pointwise = 26 if fuel else 24           # flops per quadrature point
+    return 2 * fma + pointwise * q * q
+
+
+KERNEL_FAMILY = {"assemble_s1_fuel": "k_assemble<float,p=2,fuel=true>",
+                 "assemble_s3": "k_assemble<float,p=2,fuel=false>",
+                 "sweep_x_A": "k_sweep<float,p=2,m=17,x-lines>",
+                 "sweep_y_M": "k_sweep<float,p=2,m=17,y-lines>",
+                 "sweep_y_cn": "k_sweep<float,p=2,m=17,y-lines>"}
+SOURCES = {"k_assemble": ("assemble.hip",), "k_sweep": ("sweep_kernels.h", "sweep.hip")}
+
+
+def measured_traffic(kernel, nel):
+    """HBM bytes per launch from the committed counter summary, or None when
+    there is none for this workload or the kernel's sources changed since."""
+    import hashlib
+    import re
+    path = os.path.join(ROOT, "profiles", f"hbm_traffic_regional_strang_{nel}_fp32.md")
+    if not os.path.exists(path):
+        return None
+    m = re.search(r"```json\n(.*?)\n```", open(path).read(), re.S)
+    if not m:
+        return None
+    fam = KERNEL_FAMILY[kernel]
+    ent = json.loads(m.group(1))["kernels"].get(fam)
+    if ent is None:
+        return None
+    h = hashlib.sha256()
+    for f in SOURCES[fam.split("<")[0]]:
+        h.update(open(os.path.join(ROOT, "paper_2604_19370_amd", "csrc", f), "rb").read())
+    return ent["traffic_bytes"] if h.hexdigest()[:16] == ent["source_hash"] else None
+
+
+def roofline(kt, p, ndof, nel, nel_x):
+    """Roofline entry of the dominant (longest) kernel of the FP32 step."""
+    w = 4
+    alg_bytes = {"assemble_s1_fuel": 4 * w * ndof, "assemble_s3": 3 * w * ndof,
+                 "sweep_x_A": 2 * w * ndof, "sweep_y_M": 2 * w * ndof, "sweep_y_cn": 2 * w * ndof}
+    dom = max(kt, key=kt.get)
+    traffic = measured_traffic(dom, nel_x)
+    roof = {"kernel": dom}
+    if dom.startswith("assemble"):
+        flops = assembly_flops(p, dom == "assemble_s1_fuel") * nel
+        achieved = flops / kt[dom] / 1e12
+        roof.update(bound="alu", achieved=round(achieved, 2), peak=FP32_VALU_PEAK, unit="TFLOP/s",
+                    frac=round(achieved / FP32_VALU_PEAK, 4),
+                    traffic=traffic,
+                    hbm_gbs=round(alg_bytes[dom] / kt[dom] / 1e9, 1),
+                    hbm_frac=round(alg_bytes[dom] / kt[dom] / 1e9 / HBM_PEAK_GBS, 4),
+                    flops_per_element=assembly_flops(p, dom == "assemble_s1_fuel"),
+                    peak_non_packed=FP32_VALU_PEAK / 2)
+    else:
+        achieved = alg_bytes[dom] / kt[dom] / 1e9
+        roof.update(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                    frac=round(achieved / HBM_PEAK_GBS, 4), traffic=traffic)
+    roof["avg_us"] = round(kt[dom] * 1e6, 2)
+    roof["kernel_us"] = {k: round(v * 1e6, 2) for k, v in kt.items()}
+    return roof
+
+
+def copy_kernel(n_bytes, reps, torch):
+    """Plain device copy (one read and one write of n_bytes per launch): the
+    calibration kernel for the profiler's FETCH_SIZE / WRITE_SIZE counters."""
+    src = torch.ones(n_bytes // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(reps):
+        torch.neg(src, out=dst)
+    torch.cuda.synchronize()
+
+
+def apply_schedule(pl, spec):
+    xl, xw, yl, yw, ar = (int(v) for v in spec.split(","))
+    pl.set_schedule(0, xl, xw)
+    pl.set_schedule(1, yl, yw)
+    pl.set_assembly_rows(ar)
+
+
 def cpu_baseline(sc, budget_s):
     import oracle
     d = oracle.desc_from_scenario(sc)
@@ -134,6 +228,19 @@ def main():
     from paper_2604_19370_amd import iga, inputs
 
     sc = inputs.regional_strang(seed=1, nel=args.nel, steps=args.steps)
+    if args.kernels_only:
+        pl = iga.Plan.from_scenario(sc, precision="fp32")
+        pl.factor()
+        if args.schedule:
+            apply_schedule(pl, args.schedule)
+        kt = kernel_times(pl, sc, args.kernel_reps, torch)
+        copy_kernel(4 * sc.ndof, args.kernel_reps, torch)
+        print(json.dumps({"kernel_us": {k: round(v * 1e6, 2) for k, v in kt.items()},
+                          "schedules": [pl.schedule(0), pl.schedule(1),
+                                        {"assembly_rows": pl.assembly_rows}],
+                          "copy_bytes": 4 * sc.ndof}), flush=True)
+        pl.close()
+        return
     res = {}
     ktimes = {}
     for prec in ("fp32", "fp64"):
@@ -141,7 +248,10 @@ def main():
         pl.factor()
         Tt = torch.tensor(sc.T0, dtype=pl.dtype, device="cuda")
         Ft = torch.tensor(sc.fuel0, dtype=pl.dtype, device="cuda")
-        pl.autotune(Tt, Ft, reps=10)          # untimed: picks tiles / workgroup widths
+        if args.schedule:
+            apply_schedule(pl, args.schedule)
+        else:
+            pl.autotune(Tt, Ft, reps=10)      # untimed: picks tiles / workgroup widths
         del Tt, Ft
         wall, ev, T, F = time_steps(pl, sc, args.steps, args.warmup, torch)
         res[prec] = dict(wall=wall, ev=ev, dofs=sc.ndof * args.steps / wall,
@@ -149,20 +259,10 @@ def main():
         ktimes[prec] = kernel_times(pl, sc, args.kernel_reps, torch)
         pl.close()
 
-    # dominant kernel of the FP32 step: the S1 assembly (time share printed below)
-    w = 4
     kt = ktimes["fp32"]
     ndof = sc.ndof
     nel = sc.nel_x * sc.nel_y
-    dom = max(kt, key=kt.get)
-    # algorithmic bytes of the S1 assembly: read T and fuel, write R and R_fuel
-    alg_bytes = {"assemble_s1_fuel": 4 * w * ndof, "assemble_s3": 3 * w * ndof,
-                 "sweep_x_A": 2 * w * ndof, "sweep_y_M": 2 * w * ndof, "sweep_y_cn": 2 * w * ndof}
-    achieved = alg_bytes[dom] / kt[dom] / 1e9
-    roof = {"kernel": dom, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-            "avg_us": round(kt[dom] * 1e6, 2),
-            "kernel_us": {k: round(v * 1e6, 2) for k, v in kt.items()}}
+    roof = roofline(kt, sc.p, ndof, nel, sc.nel_x)
 
     line = {
         "metric": "DOF-steps/s at 1024^2 quadratic IGA (Strang-CN), FP32+refine; FP64 beside",
@@ -183,6 +283,9 @@ def main():
                  "ms_per_step": round(res["fp64"]["wall"] / args.steps * 1e3, 5),
                  "kernel_us": {k: round(v * 1e6, 2) for k, v in ktimes["fp64"].items()}},
         "fp32_over_fp64": round(res["fp32"]["dofs"] / res["fp64"]["dofs"], 3),
+        # whole step against HBM: 15 fields of 4 B move per DOF-step in the
+        # fused minimum of a Strang step
+        "step_hbm_frac": round(res["fp32"]["dofs"] * 60 / (HBM_PEAK_GBS * 1e9), 4),
         "roofline": roof,
         "schedules": res["fp32"]["sched"],
     }
