@@ -16,15 +16,26 @@
 //
 // Schedule: one wavefront owns a strip of 64 element columns (lane = element
 // column ey, the strip's first p lanes are halo) and marches along x over a
-// tile of element rows.  Per step it loads one new coefficient row of S and
-// fuel (coalesced), contracts it in y with the lane's own basis table (the
-// y half of the sum factorisation, reused by the p+1 elements that share the
-// row), finishes the x half with the element row's basis table held in scalar
-// registers, evaluates the pointwise terms at the (p+1)^2 points, and
-// accumulates the x half of the test-function contraction into rolling
-// per-row accumulators.  When a dof row is complete its y contraction is
-// gathered from the p neighbouring lanes and stored.  Every dof is summed by
-// exactly one lane in a fixed order: no atomics, deterministic.
+// tile of element rows.  Per step it takes one new coefficient row of S and
+// fuel (loaded p+1 rows ahead, coalesced), contracts it in y with the lane's
+// own basis table (the y half of the sum factorisation, reused by the p+1
+// elements that share the row; neighbouring columns arrive by DPP rotates),
+// finishes the x half with the element row's basis table in scalar
+// registers, evaluates the pointwise terms at the (p+1)^2 points and
+// accumulates the x half of the test-function contraction into per-row
+// accumulators.  When a dof row is complete its y contraction is gathered from
+// the p neighbouring lanes and stored.  Every dof is summed by exactly one lane
+// in a fixed order: no atomics, deterministic.
+//
+// The marching loop is unrolled by p+1, so the rolling windows (coefficient
+// rows, accumulators, pending loads) are renamed, not copied.  The x
+// quadrature weight is folded into the pointwise coefficients, the y weight
+// into the completed row.  The ignition indicator needs S > T_ig somewhere in
+// the element; S is a convex combination of the element's coefficients
+// (B-splines are non-negative and sum to one), so where no coefficient of any
+// element of the wavefront's row exceeds T_ig (less a rounding margin) the
+// Arrhenius term is zero and the fuel terms that only it feeds are skipped.
+#include "dpp.h"
 #include "iga_internal.h"
 
 namespace iga {
@@ -34,24 +45,22 @@ template <typename T> struct AsmParams {
     T *R, *RF;
     const T *bx, *by;   // [e][2][Q][Q]: (values, derivatives)[a][q]
     const T *wx, *wy;   // (b_y(x) - bbar_y) at x-points, (b_x(y) - bbar_x) at y-points
-    T w[16];            // w_qx w_qy |J| per point (uniform mesh)
-    // integrand  a0 v + ax v_x + ay v_y  with
-    //   a0 = cs S - cx S_x - cy S_y + beta f,  ax = -(dx + beta g) S_x,  ay = -(dy + beta g) S_y
-    T cs, cx, cy, dx, dy, beta;
-    T c_adv, c_nld, c_ign, t_ig, fthr, t_act, c_forc, c_rad;
-    T cf, fuel_dt_rate;   // fuel: a0f = F (cf - tau rate arr)
+    T wxq[4], wyq[4];   // Gauss weight * h/2 per point and direction (uniform mesh)
+    // integrand  a0 v + ax v_x + ay v_y, weighted by wxq[qx] here:
+    //   a0 = cs S + (-cx - beta c_adv wy) S_x + (-cy - beta c_adv wx) S_y
+    //        + beta (c_forc - c_rad S^4 + c_ign arr)
+    //   ax = -(dx + beta c_nld S^3) S_x,  ay = -(dy + beta c_nld S^3) S_y
+    // fuel: af = F (cf - tau rate arr)
+    T cs_w[4], frc_w[4], rad_w[4], nld_w[4], dx_w[4], dy_w[4], ign_w[4], cf_w[4], rate_w[4];
+    T cx, cy, bca;      // bca = beta c_adv
+    T t_ig, t_skip, fthr, t_act;
+    int fuel_all;       // fuel right-hand side nonzero without ignition (direct form)
     int nel_x, nel_y, Nx, Ny, rows, nstrips, ntiles;
 };
 
-template <typename T> __device__ __forceinline__ T shfl(T v, int src)
-{
-    return __shfl(v, src, 64);
-}
-
-template <typename T> __device__ __forceinline__ T arrhenius(T S, T t_act)
-{
-    return S * exp(-t_act / S);
-}
+template <int N> struct Ic {
+    static constexpr int value = N;
+};
 
 template <typename T, int P, bool FUEL>
 __global__ __launch_bounds__(256) void k_assemble(AsmParams<T> a)
@@ -68,7 +77,7 @@ __global__ __launch_bounds__(256) void k_assemble(AsmParams<T> a)
     const int colA = J0 - P + lane, colB = colA + 64;
     const bool okA = colA >= 0 && colA < Ny, okB = lane < P && colB < Ny;
 
-    T byv[Q][Q], byd[Q][Q], wyr[Q];
+    T byv[Q][Q], byd[Q][Q], kxw[Q][Q];
 #pragma unroll
     for (int b = 0; b < Q; ++b)
 #pragma unroll
@@ -77,7 +86,11 @@ __global__ __launch_bounds__(256) void k_assemble(AsmParams<T> a)
             byd[b][q] = eyok ? a.by[(((size_t)ey * 2 + 1) * Q + b) * Q + q] : T(0);
         }
 #pragma unroll
-    for (int q = 0; q < Q; ++q) wyr[q] = eyok ? a.wy[(size_t)ey * Q + q] : T(0);
+    for (int qy = 0; qy < Q; ++qy) {
+        const T k = -a.cx - a.bca * (eyok ? a.wy[(size_t)ey * Q + qy] : T(0));
+#pragma unroll
+        for (int qx = 0; qx < Q; ++qx) kxw[qx][qy] = k * a.wxq[qx];
+    }
 
     // raw coefficients of row `row` for columns colA (and colB for the halo)
     auto fetch = [&](int row, T &c0, T &c1, T &f0, T &f1) {
@@ -94,19 +107,25 @@ __global__ __launch_bounds__(256) void k_assemble(AsmParams<T> a)
             }
         }
     };
-    // y half of the sum factorisation of one fetched row
-    auto ytransform = [&](T c0, T c1, T f0, T f1, T(&v)[Q], T(&d)[Q], T(&f)[Q]) {
+    // y half of the sum factorisation of one fetched row, and the largest
+    // coefficient of the row within the lane's element
+    auto ytransform = [&](T c0, T c1, T f0, T f1, T(&v)[Q], T(&d)[Q], T(&f)[Q], T &mx) {
         T cb[Q], fb[Q];
         cb[0] = c0;
         fb[0] = f0;
-#pragma unroll
-        for (int b = 1; b < Q; ++b) {
-            const int src = lane + b;
-            const T u0 = shfl(c0, src & 63), u1 = shfl(c1, (src - 64) & 63);
-            const T g0 = shfl(f0, src & 63), g1 = shfl(f1, (src - 64) & 63);
-            cb[b] = src < 64 ? u0 : u1;
-            fb[b] = src < 64 ? g0 : g1;
+        cb[1] = lane_ahead<1>(c0, c1, lane);
+        fb[1] = lane_ahead<1>(f0, f1, lane);
+        if (Q > 2) {
+            cb[2] = lane_ahead<2>(c0, c1, lane);
+            fb[2] = lane_ahead<2>(f0, f1, lane);
         }
+        if (Q > 3) {
+            cb[Q - 1] = lane_ahead<(Q > 3 ? 3 : 1)>(c0, c1, lane);
+            fb[Q - 1] = lane_ahead<(Q > 3 ? 3 : 1)>(f0, f1, lane);
+        }
+        mx = cb[0];
+#pragma unroll
+        for (int b = 1; b < Q; ++b) mx = fmax(mx, cb[b]);
 #pragma unroll
         for (int q = 0; q < Q; ++q) {
             T sv = 0, sd = 0, sf = 0;
@@ -124,132 +143,170 @@ __global__ __launch_bounds__(256) void k_assemble(AsmParams<T> a)
 
     const int X0 = tile * a.rows;
     const int X1 = min(X0 + a.rows, a.Nx);
-    T tv[Q][Q], td[Q][Q], tf[Q][Q];
+    const int K = X1 - (X0 - P);   // marching steps: element rows X0-P .. X1-1
+    // rings indexed by (step + i) mod Q
+    T tv[Q][Q], td[Q][Q], tf[Q][Q], rmx[Q];
     T acc0[Q][Q], acc1[Q][Q], accf[Q][Q];
+    T pc0[Q], pc1[Q], pf0[Q], pf1[Q];
 #pragma unroll
     for (int i = 0; i < Q; ++i)
 #pragma unroll
         for (int q = 0; q < Q; ++q) acc0[i][q] = acc1[i][q] = accf[i][q] = T(0);
+    // window rows X0-P .. X0-1 in slots 0 .. P-1
 #pragma unroll
     for (int s = 0; s < P; ++s) {
         T c0, c1, f0, f1;
         fetch(X0 - P + s, c0, c1, f0, f1);
-        ytransform(c0, c1, f0, f1, tv[s], td[s], tf[s]);
+        ytransform(c0, c1, f0, f1, tv[s], td[s], tf[s], rmx[s]);
     }
-    // coefficient rows are fetched two element rows ahead, the element row's
-    // x basis table one row ahead, so neither load latency is exposed
-    T nc0, nc1, nf0, nf1, mc0, mc1, mf0, mf1;
-    fetch(X0, nc0, nc1, nf0, nf1);
-    fetch(X0 + 1, mc0, mc1, mf0, mf1);
-    auto xtab = [&](int ex, T(&v)[Q][Q], T(&dv)[Q][Q], T(&w)[Q]) {
-        const int e = ex < 0 ? 0 : (ex >= a.nel_x ? a.nel_x - 1 : ex);
-        const T *bxe = a.bx + (size_t)e * 2 * Q * Q;
+    // pending loads: step k consumes row X0 + k from slot k mod Q
 #pragma unroll
-        for (int i = 0; i < Q; ++i)
-#pragma unroll
-            for (int q = 0; q < Q; ++q) {
-                v[i][q] = bxe[i * Q + q];
-                dv[i][q] = bxe[Q * Q + i * Q + q];
-            }
-#pragma unroll
-        for (int q = 0; q < Q; ++q) w[q] = a.wx[(size_t)e * Q + q];
-    };
-    T bxv[Q][Q], bxd[Q][Q], wxr[Q];
-    xtab(X0 - P, bxv, bxd, wxr);
+    for (int s = 0; s < Q; ++s) fetch(X0 + s, pc0[s], pc1[s], pf0[s], pf1[s]);
 
-    for (int ex = X0 - P; ex < X1; ++ex) {
-        const T c0 = nc0, c1 = nc1, f0 = nf0, f1 = nf1;
-        nc0 = mc0; nc1 = mc1; nf0 = mf0; nf1 = mf1;
-        fetch(ex + P + 2, mc0, mc1, mf0, mf1);
-        T nbxv[Q][Q], nbxd[Q][Q], nwxr[Q];
-        xtab(ex + 1, nbxv, nbxd, nwxr);
-        ytransform(c0, c1, f0, f1, tv[P], td[P], tf[P]);
+    const T t_skip = a.t_skip;
+    auto step = [&](auto phase, int k) {
+        constexpr int ph = decltype(phase)::value;
+        constexpr int snew = (ph + P) % Q;   // slot of the new coefficient row / dof row ex+P
+        const int ex = X0 - P + k;
+        ytransform(pc0[ph], pc1[ph], pf0[ph], pf1[ph], tv[snew], td[snew], tf[snew], rmx[snew]);
+        fetch(ex + P + Q, pc0[ph], pc1[ph], pf0[ph], pf1[ph]);
         if (ex >= 0 && ex < a.nel_x) {
+            const int e2 = (ex >= P && ex < a.nel_x - P) ? P : ex;   // interior tables coincide
+            const T *bxe = a.bx + (size_t)e2 * 2 * Q * Q;
+            T bxv[Q][Q], bxd[Q][Q], kyw[Q];
+#pragma unroll
+            for (int i = 0; i < Q; ++i)
+#pragma unroll
+                for (int q = 0; q < Q; ++q) {
+                    bxv[i][q] = bxe[i * Q + q];
+                    bxd[i][q] = bxe[Q * Q + i * Q + q];
+                }
+#pragma unroll
+            for (int q = 0; q < Q; ++q)
+                kyw[q] = (-a.cy - a.bca * a.wx[(size_t)ex * Q + q]) * a.wxq[q];
+            T emx = rmx[0];
+#pragma unroll
+            for (int s = 1; s < Q; ++s) emx = fmax(emx, rmx[s]);
+            const bool hot = FUEL ? (a.fuel_all || __any(emx > t_skip)) : __any(emx > t_skip);
+            // linear, loss, forcing, wind and T^3-diffusion terms; the first
+            // contribution to the fresh dof row (slot snew) is assigned
 #pragma unroll
             for (int qx = 0; qx < Q; ++qx) {
 #pragma unroll
                 for (int qy = 0; qy < Q; ++qy) {
-                    T S = 0, Sx = 0, Sy = 0, F = 0;
+                    T S = 0, Sx = 0, Sy = 0;
 #pragma unroll
                     for (int i = 0; i < Q; ++i) {
-                        S += bxv[i][qx] * tv[i][qy];
-                        Sx += bxd[i][qx] * tv[i][qy];
-                        Sy += bxv[i][qx] * td[i][qy];
-                        F += bxv[i][qx] * tf[i][qy];
+                        const int si = (ph + i) % Q;
+                        S += bxv[i][qx] * tv[si][qy];
+                        Sx += bxd[i][qx] * tv[si][qy];
+                        Sy += bxv[i][qx] * td[si][qy];
                     }
-                    const T W = a.w[qx * Q + qy];
+                    // chains ordered so that no instruction reads two scalar operands
                     const T S2 = S * S;
-                    const T g = a.c_nld * S2 * S;
-                    T f = a.c_forc - a.c_rad * S2 * S2 - a.c_adv * (wyr[qy] * Sx + wxr[qx] * Sy);
-                    T arr = T(0);
-                    if (S > a.t_ig && F > a.fthr) arr = arrhenius(S, a.t_act);
-                    f += a.c_ign * arr;
-                    const T a0 = W * (a.cs * S - a.cx * Sx - a.cy * Sy + a.beta * f);
-                    const T bg = a.beta * g;
-                    const T ax = -W * (a.dx + bg) * Sx;
-                    const T ay = -W * (a.dy + bg) * Sy;
+                    const T g = a.nld_w[qx] * (S2 * S);
+                    T a0 = kyw[qx] * Sy + a.frc_w[qx];
+                    a0 += a.rad_w[qx] * (S2 * S2);
+                    a0 += a.cs_w[qx] * S;
+                    a0 += kxw[qx][qy] * Sx;
+                    const T ax = (g + a.dx_w[qx]) * Sx;
+                    const T ay = (g + a.dy_w[qx]) * Sy;
 #pragma unroll
                     for (int i = 0; i < Q; ++i) {
-                        acc0[i][qy] += a0 * bxv[i][qx] + ax * bxd[i][qx];
-                        acc1[i][qy] += ay * bxv[i][qx];
-                    }
-                    if (FUEL) {
-                        const T af = W * F * (a.cf - a.fuel_dt_rate * arr);
-#pragma unroll
-                        for (int i = 0; i < Q; ++i) accf[i][qy] += af * bxv[i][qx];
+                        const int si = (ph + i) % Q;
+                        if (i == P && qx == 0) {
+                            acc0[si][qy] = a0 * bxv[i][qx] + ax * bxd[i][qx];
+                            acc1[si][qy] = ay * bxv[i][qx];
+                        } else {
+                            acc0[si][qy] += a0 * bxv[i][qx] + ax * bxd[i][qx];
+                            acc1[si][qy] += ay * bxv[i][qx];
+                        }
                     }
                 }
             }
+            if (hot) {
+                // ignition source and fuel terms (S and fuel re-evaluated)
+#pragma unroll
+                for (int qx = 0; qx < Q; ++qx) {
+#pragma unroll
+                    for (int qy = 0; qy < Q; ++qy) {
+                        T S = 0, F = 0;
+#pragma unroll
+                        for (int i = 0; i < Q; ++i) {
+                            const int si = (ph + i) % Q;
+                            S += bxv[i][qx] * tv[si][qy];
+                            F += bxv[i][qx] * tf[si][qy];
+                        }
+                        T arr = T(0);
+                        if (S > a.t_ig && F > a.fthr) arr = S * exp(-a.t_act / S);
+                        const T a0 = a.ign_w[qx] * arr;
+                        const T af = F * (a.cf_w[qx] - a.rate_w[qx] * arr);
+#pragma unroll
+                        for (int i = 0; i < Q; ++i) {
+                            const int si = (ph + i) % Q;
+                            acc0[si][qy] += a0 * bxv[i][qx];
+                            if (FUEL) accf[si][qy] += af * bxv[i][qx];
+                        }
+                    }
+                }
+            }
+        } else {
+#pragma unroll
+            for (int q = 0; q < Q; ++q) acc0[snew][q] = acc1[snew][q] = T(0);
         }
         if (ex >= X0) {
-            // dof row ex is complete: y half of the test contraction
+            // dof row ex (slot ph) is complete: y weights, y half of the test
+            // contraction, gather from the p lanes to the left
+            constexpr int sd = ph;
             T pb[Q], pf[Q];
+#pragma unroll
+            for (int q = 0; q < Q; ++q) {
+                acc0[sd][q] *= a.wyq[q];
+                acc1[sd][q] *= a.wyq[q];
+                if (FUEL) accf[sd][q] *= a.wyq[q];
+            }
 #pragma unroll
             for (int b = 0; b < Q; ++b) {
                 T s0 = 0, s1 = 0;
 #pragma unroll
                 for (int q = 0; q < Q; ++q) {
-                    s0 += acc0[0][q] * byv[b][q] + acc1[0][q] * byd[b][q];
-                    if (FUEL) s1 += accf[0][q] * byv[b][q];
+                    s0 += acc0[sd][q] * byv[b][q] + acc1[sd][q] * byd[b][q];
+                    if (FUEL) s1 += accf[sd][q] * byv[b][q];
                 }
                 pb[b] = s0;
                 pf[b] = s1;
             }
-            T r = pb[0], rf = pf[0];
-#pragma unroll
-            for (int b = 1; b < Q; ++b) {
-                r += shfl(pb[b], (lane - b) & 63);
-                if (FUEL) rf += shfl(pf[b], (lane - b) & 63);
+            T r = pb[0] + lane_behind<1>(pb[1]);
+            T rf = FUEL ? pf[0] + lane_behind<1>(pf[1]) : T(0);
+            if (Q > 2) {
+                r += lane_behind<2>(pb[2]);
+                if (FUEL) rf += lane_behind<2>(pf[2]);
+            }
+            if (Q > 3) {
+                r += lane_behind<(Q > 3 ? 3 : 1)>(pb[Q - 1]);
+                if (FUEL) rf += lane_behind<(Q > 3 ? 3 : 1)>(pf[Q - 1]);
             }
             if (lane >= P && colA < Ny) {
                 a.R[(size_t)ex * Ny + colA] = r;
                 if (FUEL) a.RF[(size_t)ex * Ny + colA] = rf;
             }
         }
-        // roll the windows
+        if (FUEL) {
 #pragma unroll
-        for (int i = 0; i < Q; ++i) {
-#pragma unroll
-            for (int q = 0; q < Q; ++q) {
-                bxv[i][q] = nbxv[i][q];
-                bxd[i][q] = nbxd[i][q];
-            }
-            wxr[i] = nwxr[i];
+            for (int q = 0; q < Q; ++q) accf[ph][q] = T(0);
         }
-#pragma unroll
-        for (int s = 0; s < P; ++s)
-#pragma unroll
-            for (int q = 0; q < Q; ++q) {
-                tv[s][q] = tv[s + 1][q];
-                td[s][q] = td[s + 1][q];
-                tf[s][q] = tf[s + 1][q];
-                acc0[s][q] = acc0[s + 1][q];
-                acc1[s][q] = acc1[s + 1][q];
-                accf[s][q] = accf[s + 1][q];
-            }
-#pragma unroll
-        for (int q = 0; q < Q; ++q) acc0[P][q] = acc1[P][q] = accf[P][q] = T(0);
+    };
+
+    int k = 0;
+    for (; k + Q <= K; k += Q) {
+        step(Ic<0>{}, k);
+        step(Ic<1>{}, k + 1);
+        step(Ic<2>{}, k + 2);
+        if (Q > 3) step(Ic<(Q > 3 ? 3 : 0)>{}, k + 3);
     }
+    if (k < K) step(Ic<0>{}, k);
+    if (k + 1 < K) step(Ic<1>{}, k + 1);
+    if (Q > 3 && k + 2 < K) step(Ic<2>{}, k + 2);
 }
 
 template <typename T>
@@ -268,8 +325,6 @@ static iga_status launch_t(const iga_plan *pl, int substep, const void *S, const
     a.by = pl->asm_by.as<T>();
     a.wx = pl->asm_wx.as<T>();
     a.wy = pl->asm_wy.as<T>();
-    for (int qx = 0; qx < Q; ++qx)
-        for (int qy = 0; qy < Q; ++qy) a.w[qx * Q + qy] = (T)(pl->X.wq[qx] * pl->Y.wq[qy]);
     // weights of the explicit (kx_e, ky_e) and implicit (kx_i, ky_i) parts of
     // the linear operator in this substep, and of F (beta)
     double kx_e = 0, ky_e = 0, kx_i = 0, ky_i = 0, beta;
@@ -285,34 +340,44 @@ static iga_status launch_t(const iga_plan *pl, int substep, const void *S, const
         beta = 0.5 * d.dt;
     }
     const double react = d.c.c_react;
-    double cs, kx, ky;
+    double cs, kx, ky, cf;
     if (pl->delta) {
         // increment form: R - (implicit operator) S
         kx = kx_e + kx_i;
         ky = ky_e + ky_i;
         cs = kx * react;
-        a.cf = T(0);
+        cf = 0.0;
     } else {
         kx = kx_e;
         ky = ky_e;
         cs = 1.0 + kx * react;
-        a.cf = T(1);
+        cf = 1.0;
     }
-    a.cs = (T)cs;
+    const double dx = kx * d.c.c_diff, dy = ky * d.c.c_diff;
+    for (int q = 0; q < Q; ++q) {
+        const double w = pl->X.wq[q];
+        a.wxq[q] = (T)w;
+        a.wyq[q] = (T)pl->Y.wq[q];
+        a.cs_w[q] = (T)(cs * w);
+        a.frc_w[q] = (T)(beta * d.c.c_forcing * w);
+        a.rad_w[q] = (T)(-beta * d.c.c_rad * w);
+        a.nld_w[q] = (T)(-beta * d.c.c_nld * w);
+        a.dx_w[q] = (T)(-dx * w);
+        a.dy_w[q] = (T)(-dy * w);
+        a.ign_w[q] = (T)(beta * d.c.c_ign * w);
+        a.cf_w[q] = (T)(cf * w);
+        a.rate_w[q] = (T)(d.dt * d.c.fuel_rate * w);
+    }
     a.cx = (T)(kx * d.c.c_adv * d.wind.bbar_x);
     a.cy = (T)(ky * d.c.c_adv * d.wind.bbar_y);
-    a.dx = (T)(kx * d.c.c_diff);
-    a.dy = (T)(ky * d.c.c_diff);
-    a.beta = (T)beta;
-    a.c_adv = (T)d.c.c_adv;
-    a.c_nld = (T)d.c.c_nld;
-    a.c_ign = (T)d.c.c_ign;
+    a.bca = (T)(beta * d.c.c_adv);
     a.t_ig = (T)d.c.t_ig;
+    // S exceeds the largest coefficient of its element by at most a few
+    // roundings of the basis contraction; skip only well below T_ig
+    a.t_skip = (T)(d.c.t_ig - 1e-4 * std::fabs(d.c.t_ig));
     a.fthr = (T)d.c.fuel_thr;
     a.t_act = (T)d.c.t_act;
-    a.c_forc = (T)d.c.c_forcing;
-    a.c_rad = (T)d.c.c_rad;
-    a.fuel_dt_rate = (T)(d.dt * d.c.fuel_rate);
+    a.fuel_all = cf != 0.0;
     a.nel_x = d.nel_x;
     a.nel_y = d.nel_y;
     a.Nx = pl->Nx;
