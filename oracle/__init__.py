@@ -75,6 +75,8 @@ def lib() -> ctypes.CDLL:
         L.oracle_line_solve.argtypes = [ctypes.POINTER(Desc), ctypes.c_int, ctypes.c_int, dp]
         L.oracle_assemble.argtypes = [ctypes.POINTER(Desc), ctypes.c_int, dp, dp, dp, dp]
         L.oracle_step.argtypes = [ctypes.POINTER(Desc), dp, dp]
+        L.oracle_step_flagged.argtypes = [ctypes.POINTER(Desc), dp, dp, ctypes.c_double,
+                                          ctypes.c_double, ctypes.c_void_p]
         L.oracle_run.argtypes = [ctypes.POINTER(Desc), dp, dp, ctypes.c_int]
         L.oracle_eval_grid.argtypes = [ctypes.POINTER(Desc), dp, dp, ctypes.c_int, dp,
                                        ctypes.c_int, dp]
@@ -192,6 +194,17 @@ def step(desc: Desc, T: np.ndarray, fuel: np.ndarray):
     fuel = np.array(fuel, dtype=np.float64, order="C", copy=True)
     _check(lib().oracle_step(ctypes.byref(desc), _p(T), _p(fuel)), "step")
     return T, fuel
+
+
+def step_flagged(desc: Desc, T: np.ndarray, fuel: np.ndarray, dT: float, dF: float):
+    """One step, plus a boolean (nel_x, nel_y) map of the elements where the
+    ignition decision of some substep lies within (dT, dF) of its thresholds."""
+    T = np.array(T, dtype=np.float64, order="C", copy=True)
+    fuel = np.array(fuel, dtype=np.float64, order="C", copy=True)
+    flags = np.zeros((desc.nel_x, desc.nel_y), dtype=np.uint8)
+    _check(lib().oracle_step_flagged(ctypes.byref(desc), _p(T), _p(fuel), float(dT), float(dF),
+                                     flags.ctypes.data_as(ctypes.c_void_p)), "step_flagged")
+    return T, fuel, flags.astype(bool)
 
 
 def run(desc: Desc, T: np.ndarray, fuel: np.ndarray, nsteps: int):

@@ -395,9 +395,17 @@ static void wind_at(const oracle_desc *d, double x, double y, double *bx, double
  *       + [S > T_ig and fuel > thr] C_ign S exp(-T_act / S)
  * and, when rhs_fuel is given, the fuel right-hand side of the compute_rhs
  * listing,  fuel v - tau * rate * [ign] S exp(-T_act/S) fuel v. */
+/* Elements whose ignition decision is within (dT, dF) of its thresholds at
+ * some quadrature point (test support: there a lower-precision evaluation of
+ * S or fuel may legitimately decide the other way). */
+typedef struct {
+    double dT, dF;
+    unsigned char *flags;   /* [nel_x][nel_y], set to 1, never cleared */
+} ambiguity;
+
 static int assemble_quadrature(const oracle_desc *d, int edir, double alpha,
                                double beta, const double *T, const double *fuel,
-                               double *rhs_T, double *rhs_fuel)
+                               double *rhs_T, double *rhs_fuel, const ambiguity *amb)
 {
     int p = d->p, nq = p + 1;
     int Ny = d->nel_y + p, Nx = d->nel_x + p;
@@ -435,6 +443,9 @@ static int assemble_quadrature(const oracle_desc *d, int edir, double alpha,
                         double bxv, byv;
                         wind_at(d, X.xq[eqx], Y.xq[eqy], &bxv, &byv);
                         int ign = (S > c->t_ig) && (Fu > c->fuel_thr);
+                        if (amb && ((fabs(S - c->t_ig) <= amb->dT && Fu > c->fuel_thr - amb->dF) ||
+                                    (fabs(Fu - c->fuel_thr) <= amb->dF && S > c->t_ig - amb->dT)))
+                            amb->flags[(size_t)ex * d->nel_y + ey] = 1;
                         double arr = ign ? S * exp(-c->t_act / S) : 0.0;
                         double S2 = S * S;
                         double f = -c->c_adv * ((bxv - d->bbar_x) * Sx + (byv - d->bbar_y) * Sy)
@@ -514,7 +525,19 @@ int oracle_assemble(const oracle_desc *d, int substep, const double *T,
     int edir;
     double alpha, beta;
     if (substep_params(d, substep, &edir, &alpha, &beta)) return 1;
-    return assemble_quadrature(d, edir, alpha, beta, T, fuel, rhs_T, rhs_fuel);
+    return assemble_quadrature(d, edir, alpha, beta, T, fuel, rhs_T, rhs_fuel, NULL);
+}
+
+static int assemble_checked(const oracle_desc *d, int substep, const double *T,
+                            const double *fuel, double *rhs_T, double *rhs_fuel,
+                            const ambiguity *amb)
+{
+    if (!amb || (d->scheme == ORACLE_STRANG && substep == 1))
+        return oracle_assemble(d, substep, T, fuel, rhs_T, rhs_fuel);
+    int edir;
+    double alpha, beta;
+    if (substep_params(d, substep, &edir, &alpha, &beta)) return 1;
+    return assemble_quadrature(d, edir, alpha, beta, T, fuel, rhs_T, rhs_fuel, amb);
 }
 
 /* (A (x) B) X = R: solve A along the x-lines, then B along the y-lines. */
@@ -525,7 +548,7 @@ static int kron_solve(const oracle_desc *d, int which_x, int which_y, double *X)
     return rc;
 }
 
-int oracle_step(const oracle_desc *d, double *T, double *fuel)
+static int step_impl(const oracle_desc *d, double *T, double *fuel, const ambiguity *amb)
 {
     if (!valid_desc(d) || !T || !fuel) return 1;
     size_t n = (size_t)(d->nel_x + d->p) * (d->nel_y + d->p);
@@ -535,19 +558,19 @@ int oracle_step(const oracle_desc *d, double *T, double *fuel)
     int rc;
     if (d->scheme == ORACLE_PR) {
         /* eq. (matrixPR): [A^x (x) M^y] T^{n+1/2} = ..., [M^x (x) A^y] T^{n+1} = ... */
-        rc = oracle_assemble(d, 0, T, fuel, R, RF);
+        rc = assemble_checked(d, 0, T, fuel, R, RF, amb);
         if (!rc) rc = kron_solve(d, 0, 1, R);
         if (!rc) memcpy(T, R, sizeof(double) * n);
-        if (!rc) rc = oracle_assemble(d, 1, T, fuel, R, NULL);
+        if (!rc) rc = assemble_checked(d, 1, T, fuel, R, NULL, amb);
         if (!rc) rc = kron_solve(d, 1, 0, R);
         if (!rc) memcpy(T, R, sizeof(double) * n);
     } else {
         /* eq. (matrixCN): T^n -> T* -> T** -> T^{n+1} */
-        rc = oracle_assemble(d, 0, T, fuel, R, RF);
+        rc = assemble_checked(d, 0, T, fuel, R, RF, amb);
         if (!rc) rc = kron_solve(d, 0, 1, R);
         if (!rc) rc = oracle_assemble(d, 1, R, fuel, T, NULL);
         if (!rc) rc = kron_solve(d, 1, 0, T);
-        if (!rc) rc = oracle_assemble(d, 2, T, fuel, R, NULL);
+        if (!rc) rc = assemble_checked(d, 2, T, fuel, R, NULL, amb);
         if (!rc) rc = kron_solve(d, 0, 1, R);
         if (!rc) memcpy(T, R, sizeof(double) * n);
     }
@@ -557,6 +580,19 @@ int oracle_step(const oracle_desc *d, double *T, double *fuel)
     free(R);
     free(RF);
     return rc;
+}
+
+int oracle_step(const oracle_desc *d, double *T, double *fuel)
+{
+    return step_impl(d, T, fuel, NULL);
+}
+
+int oracle_step_flagged(const oracle_desc *d, double *T, double *fuel, double dT, double dF,
+                        unsigned char *flags)
+{
+    if (!flags || !(dT >= 0) || !(dF >= 0)) return 1;
+    ambiguity amb = {dT, dF, flags};
+    return step_impl(d, T, fuel, &amb);
 }
 
 int oracle_run(const oracle_desc *d, double *T, double *fuel, int nsteps)

@@ -75,6 +75,12 @@ int oracle_assemble(const oracle_desc *d, int substep, const double *T,
                     const double *fuel, double *rhs_T, double *rhs_fuel);
 /* One full time step, in place. */
 int oracle_step(const oracle_desc *d, double *T, double *fuel);
+/* oracle_step, and flags[ex * nel_y + ey] = 1 for every element with a
+ * quadrature point, in any substep, where the ignition decision is within dT
+ * of T_ig (with fuel above thr - dF) or within dF of the fuel threshold (with
+ * S above T_ig - dT).  flags is not cleared first. */
+int oracle_step_flagged(const oracle_desc *d, double *T, double *fuel, double dT, double dF,
+                        unsigned char *flags);
 int oracle_run(const oracle_desc *d, double *T, double *fuel, int nsteps);
 /* Evaluate the spline with coefficients C at the tensor grid xs x ys
  * (out[a * ny + b]). */

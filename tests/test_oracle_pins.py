@@ -453,3 +453,37 @@ def test_eval_grid_and_burned_fraction():
     C[:5] = 0.0   # zero coefficients for x-functions 0..4 -> element columns 0..2 fully zero
     bfrac = oracle.burned_fraction(d, C, 0.1)
     assert 3 / 8 <= bfrac <= 5 / 8
+
+
+@pytest.mark.parametrize("scheme", ["pr", "strang"])
+def test_step_flagged_marks_ambiguous_ignition_decisions(scheme):
+    """The flagged step returns the plain step's result and marks exactly the
+    elements where some quadrature point's ignition decision is within the
+    given distance of a threshold.  Expected sets follow from partition of
+    unity (a constant coefficient field is that constant at every point) and
+    from S being a convex combination of the element's coefficients with
+    weights bounded away from zero at Gauss points."""
+    nx, ny, p = 20, 17, 2
+    d = oracle.make_desc(nx, ny, p, float(nx), float(ny), 1e-3, scheme)
+    shape = (nx + p, ny + p)
+    ones = np.ones(shape)
+    # T == T_ig everywhere: every element is on the threshold
+    T, F, fl = oracle.step_flagged(d, 800.0 * ones, ones, 1e-9, 1e-9)
+    Tp, Fp = oracle.step(d, 800.0 * ones, ones)
+    assert np.array_equal(T, Tp) and np.array_equal(F, Fp)
+    assert fl.all()
+    # T clearly above T_ig (and heating further): no element
+    _, _, fl = oracle.step_flagged(d, 801.0 * ones, ones, 0.5, 1e-9)
+    assert not fl.any()
+    # fuel == threshold with T above T_ig: every element
+    _, _, fl = oracle.step_flagged(d, 1000.0 * ones, 0.2 * ones, 1e-9, 1e-9)
+    assert fl.all()
+    # a block of coefficients at T_ig in a 300 K field: the elements whose
+    # whole (p+1)^2 patch lies in the block, and no other (elsewhere S is at
+    # least min-weight * 500 K below T_ig at every Gauss point)
+    T0 = 300.0 * ones
+    T0[5:5 + p + 3, 4:4 + p + 2] = 800.0
+    _, _, fl = oracle.step_flagged(d, T0, ones, 1.0, 1e-9)
+    expect = np.zeros((nx, ny), dtype=bool)
+    expect[5:8, 4:6] = True
+    assert np.array_equal(fl, expect)
