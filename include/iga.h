@@ -197,6 +197,59 @@ int32_t iga_plan_assembly_rows(const iga_plan *plan);
 iga_status iga_autotune(iga_plan *plan, const void *T, const void *fuel, int32_t reps,
                         void *stream);
 
+/* ------------------------------------------------------------------------
+ * Ensembles: independent scenarios (for instance perturbed fuel maps, winds
+ * and ignitions of one region) stepped together on one GPU, each member the
+ * method of Sections 3-4 on its own mesh.  Members may differ in grid size,
+ * lengths, dt, scheme, wind, coefficients and fields, but share the degree p
+ * and the precision.  Every phase of a step (the two assemblies, the four
+ * line sweeps) runs as one launch over all members per line-solve schedule
+ * group (members with equal rows per lane, lines per workgroup and wavefronts
+ * per line), so the per-step launch count does not grow with the member
+ * count.  Each member's result is, up to rounding, the one its own plan
+ * would compute with the same line-solve schedule (the batched kernels are
+ * separately compiled and may contract multiply-adds differently).
+ * ------------------------------------------------------------------------ */
+typedef struct iga_ensemble iga_ensemble;
+
+/* Create n >= 1 member plans from members[0..n) (each checked as by
+ * iga_plan_create), factor them (as iga_factor_1d on the legacy default
+ * stream; synchronises the device), and give every member the same
+ * line-solve schedule per direction.  IGA_EINVAL if members differ in p or
+ * precision.  The ensemble owns its plans; free with iga_ensemble_destroy. */
+iga_status iga_ensemble_create(const iga_plan_desc *members, int32_t n, iga_ensemble **out);
+iga_status iga_ensemble_destroy(iga_ensemble *ens);
+iga_status iga_ensemble_size(const iga_ensemble *ens, int32_t *n);
+
+/* Kernel launches per step (2 assemblies + 2 x 2 sweeps per schedule group). */
+iga_status iga_ensemble_launches(const iga_ensemble *ens, int32_t *per_step);
+
+/* One step of every member, in place: T[m], fuel[m] are member m's fields
+ * (layout and type as for a plan of members[m]).  The pointer arrays are read
+ * during the call; the launches prepared for them are kept and reused while
+ * the same pointers are passed (rebuilt otherwise, which copies a few KB of
+ * parameters to the device and synchronises). */
+iga_status iga_ensemble_step(iga_ensemble *ens, void *const *T, void *const *fuel, void *stream);
+
+/* nsteps steps of every member, replayed from captured HIP graphs (re-captured
+ * when the pointers or the schedules change). */
+iga_status iga_ensemble_run(iga_ensemble *ens, void *const *T, void *const *fuel, int64_t nsteps,
+                            void *stream);
+
+/* Line-solve schedule of direction dir for every member: `lines` per
+ * workgroup, at least waves_per_line wavefronts per line (more for members
+ * whose lines need them).  On IGA_EUNSUPPORTED the previous schedules are
+ * restored. */
+iga_status iga_ensemble_set_schedule(iga_ensemble *ens, int32_t dir, int32_t lines,
+                                     int32_t waves_per_line);
+iga_status iga_ensemble_set_assembly_rows(iga_ensemble *ens, int32_t rows);
+
+/* Autotuner of the batched launches: element-row tiles of the assembly, and
+ * (lines, waves per line) per direction, timed with HIP events on `stream` on
+ * the members' scratch buffers (the fields are only read).  Synchronises. */
+iga_status iga_ensemble_autotune(iga_ensemble *ens, void *const *T, void *const *fuel, int32_t reps,
+                                 void *stream);
+
 /* Thread-local description of the last error ("" if none). */
 const char *iga_last_error(void);
 

@@ -36,7 +36,7 @@ void GraphEntry::reset()
 
 static bool aligned(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; }
 
-static iga_status check_desc(const iga_plan_desc *d)
+iga_status check_desc(const iga_plan_desc *d)
 {
     if (!d) return fail(IGA_EINVAL, "desc is NULL");
     if (d->p != 2 && d->p != 3) return fail(IGA_EINVAL, "p must be 2 or 3");
@@ -59,7 +59,7 @@ static iga_status check_desc(const iga_plan_desc *d)
     return IGA_OK;
 }
 
-static iga_status check_field(const void *p, const char *name)
+iga_status check_field(const void *p, const char *name)
 {
     if (!p) return fail(IGA_EINVAL, std::string(name) + " is NULL");
     if (!aligned(p)) return fail(IGA_EINVAL, std::string(name) + " is not 16-byte aligned");
@@ -69,100 +69,59 @@ static iga_status check_field(const void *p, const char *name)
 // One step in place; the right-hand sides live in the plan's scratch buffers.
 // FP32 plans advance in increment form: the assembled right-hand sides are
 // R - (implicit operator) S, the solves give the increment, and the y sweep
-// adds the state it was taken from.
-static iga_status step_impl(iga_plan *pl, void *T, void *fuel, hipStream_t s)
+// adds the state it was taken from.  A step is six launches: assembly, x
+// sweep, y sweep, twice.
+void step_phases(const iga_plan *pl, void *T, void *fuel, StepPhases &sp)
 {
     void *R = pl->scratch_r.ptr, *RF = pl->scratch_rf.ptr;
     const void *bT = pl->delta ? T : nullptr, *bF = pl->delta ? fuel : nullptr;
     const int add = pl->delta ? 1 : 0;
-    iga_status st;
     const bool pr = pl->d.scheme == IGA_PR;
     // substep 1 (PR: x implicit; Strang: S1) + the fuel right-hand side
-    if ((st = launch_assemble(pl, 0, T, fuel, R, RF, s))) return st;
-    SweepJob jx[2] = {{R, R, OP_AX, -1, -1, nullptr, 0}, {RF, RF, OP_MX, -1, -1, nullptr, 0}};
-    if ((st = launch_sweep(pl, 0, jx, 2, s))) return st;
+    sp.a1 = AsmArgs{0, T, fuel, R, RF};
+    sp.x1 = {{R, R, OP_AX, -1, -1, nullptr, 0}, {RF, RF, OP_MX, -1, -1, nullptr, 0}};
     if (pr) {
-        SweepJob jy[1] = {{R, T, OP_MY, -1, -1, bT, 0}};
-        if ((st = launch_sweep(pl, 1, jy, 1, s))) return st;
+        sp.y1 = {{R, T, OP_MY, -1, -1, bT, 0}};
         // substep 2: y implicit
-        if ((st = launch_assemble(pl, 1, T, fuel, R, nullptr, s))) return st;
-        SweepJob jx2[1] = {{R, R, OP_MX, -1, -1, nullptr, 0}};
-        if ((st = launch_sweep(pl, 0, jx2, 1, s))) return st;
-        SweepJob jy2[2] = {{R, T, OP_AY, -1, -1, bT, 0}, {RF, fuel, OP_MY, -1, -1, bF, 0}};
-        if ((st = launch_sweep(pl, 1, jy2, 2, s))) return st;
+        sp.a2 = AsmArgs{1, T, fuel, R, nullptr};
+        sp.x2 = {{R, R, OP_MX, -1, -1, nullptr, 0}};
+        sp.y2 = {{R, T, OP_AY, -1, -1, bT, 0}, {RF, fuel, OP_MY, -1, -1, bF, 0}};
     } else {
         // S1's y solve fused with S2: T** = (A^y)^{-1} B^y T* along y, with
         // T* = (M^y)^{-1} R (+ T^n in increment form)
-        SweepJob jy[1] = {{R, T, OP_MY, BAND_BY, OP_AY, bT, add}};
-        if ((st = launch_sweep(pl, 1, jy, 1, s))) return st;
+        sp.y1 = {{R, T, OP_MY, BAND_BY, OP_AY, bT, add}};
         // S3
-        if ((st = launch_assemble(pl, 2, T, fuel, R, nullptr, s))) return st;
-        SweepJob jx2[1] = {{R, R, OP_AX, -1, -1, nullptr, 0}};
-        if ((st = launch_sweep(pl, 0, jx2, 1, s))) return st;
-        SweepJob jy2[2] = {{R, T, OP_MY, -1, -1, bT, 0}, {RF, fuel, OP_MY, -1, -1, bF, 0}};
-        if ((st = launch_sweep(pl, 1, jy2, 2, s))) return st;
+        sp.a2 = AsmArgs{2, T, fuel, R, nullptr};
+        sp.x2 = {{R, R, OP_AX, -1, -1, nullptr, 0}};
+        sp.y2 = {{R, T, OP_MY, -1, -1, bT, 0}, {RF, fuel, OP_MY, -1, -1, bF, 0}};
     }
-    return IGA_OK;
 }
 
+static iga_status step_impl(iga_plan *pl, void *T, void *fuel, hipStream_t s)
+{
+    StepPhases sp;
+    step_phases(pl, T, fuel, sp);
+    iga_status st;
+    auto sweep = [&](int dir, const std::vector<SweepJob> &j) {
+        return launch_sweep(pl, dir, j.data(), (int)j.size(), s);
+    };
+    if ((st = launch_assemble(pl, sp.a1.substep, sp.a1.T, sp.a1.fuel, sp.a1.R, sp.a1.RF, s))) return st;
+    if ((st = sweep(0, sp.x1)) || (st = sweep(1, sp.y1))) return st;
+    if ((st = launch_assemble(pl, sp.a2.substep, sp.a2.T, sp.a2.fuel, sp.a2.R, sp.a2.RF, s))) return st;
+    if ((st = sweep(0, sp.x2)) || (st = sweep(1, sp.y2))) return st;
+    return IGA_OK;
+}
 
 // Capture `steps` steps on a private stream into g (kernels only; no memset
 // or host callbacks are recorded).
 static iga_status capture(iga_plan *pl, GraphEntry &g, void *T, void *fuel, int64_t steps)
 {
     if (g.exec && g.T == T && g.fuel == fuel && g.steps == steps) return IGA_OK;
-    g.reset();
-    hipStream_t cs;
-    IGA_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
-    hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
-    if (e != hipSuccess) {
-        (void)hipStreamDestroy(cs);
-        return hip_fail(e, "hipStreamBeginCapture");
-    }
-    iga_status cst = IGA_OK;
-    for (int64_t k = 0; k < steps && !cst; ++k) cst = step_impl(pl, T, fuel, cs);
-    hipGraph_t graph = nullptr;
-    e = hipStreamEndCapture(cs, &graph);
-    (void)hipStreamDestroy(cs);
-    if (cst) {
-        if (graph) (void)hipGraphDestroy(graph);
-        return cst;
-    }
-    if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
-    hipGraphExec_t exec = nullptr;
-    e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-    if (e != hipSuccess) {
-        (void)hipGraphDestroy(graph);
-        return hip_fail(e, "hipGraphInstantiate");
-    }
-    g.graph = graph;
-    g.exec = exec;
+    iga_status st = capture_graph(g, steps, [&](hipStream_t cs) { return step_impl(pl, T, fuel, cs); });
+    if (st) return st;
     g.T = T;
     g.fuel = fuel;
-    g.steps = steps;
     return IGA_OK;
-}
-
-// Time `reps` launches of fn between HIP events on s; returns ms per launch
-// (negative on failure).
-template <typename F> static float time_launches(hipStream_t s, int reps, F &&fn)
-{
-    hipEvent_t e0, e1;
-    if (hipEventCreate(&e0) != hipSuccess) return -1.f;
-    if (hipEventCreate(&e1) != hipSuccess) {
-        (void)hipEventDestroy(e0);
-        return -1.f;
-    }
-    float ms = -1.f;
-    bool ok = fn() == IGA_OK;   // warm-up
-    ok = ok && hipEventRecord(e0, s) == hipSuccess;
-    for (int i = 0; i < reps && ok; ++i) ok = fn() == IGA_OK;
-    ok = ok && hipEventRecord(e1, s) == hipSuccess && hipEventSynchronize(e1) == hipSuccess;
-    if (ok && hipEventElapsedTime(&ms, e0, e1) == hipSuccess) ms /= reps;
-    else ms = -1.f;
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
-    return ms;
 }
 
 }  // namespace iga

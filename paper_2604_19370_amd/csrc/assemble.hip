@@ -62,13 +62,12 @@ template <int N> struct Ic {
     static constexpr int value = N;
 };
 
+// The work of wavefront gw (strip gw mod nstrips, tile gw / nstrips).
 template <typename T, int P, bool FUEL>
-__global__ __launch_bounds__(256) void k_assemble(AsmParams<T> a)
+__device__ __forceinline__ void assemble_body(const AsmParams<T> &a, const int gw)
 {
     constexpr int Q = P + 1;
     const int lane = threadIdx.x & 63;
-    const int gw = blockIdx.x * (blockDim.x >> 6) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    if (gw >= a.nstrips * a.ntiles) return;
     const int strip = gw % a.nstrips, tile = gw / a.nstrips;
     const int J0 = strip * (64 - P);
     const int ey = J0 - P + lane;
@@ -309,13 +308,32 @@ __global__ __launch_bounds__(256) void k_assemble(AsmParams<T> a)
     if (Q > 3 && k + 2 < K) step(Ic<2>{}, k + 2);
 }
 
+template <typename T, int P, bool FUEL>
+__global__ __launch_bounds__(256) void k_assemble(AsmParams<T> a)
+{
+    const int gw = blockIdx.x * (blockDim.x >> 6) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    if (gw >= a.nstrips * a.ntiles) return;
+    assemble_body<T, P, FUEL>(a, gw);
+}
+
+// Batched launch over the members of an ensemble: wavefront w does wavefront
+// info[w].y of member info[w].x (x < 0: no work).
+template <typename T, int P, bool FUEL>
+__global__ __launch_bounds__(256) void k_assemble_batch(const AsmParams<T> *__restrict__ prms,
+                                                        const int2 *__restrict__ info)
+{
+    const int gw = blockIdx.x * (blockDim.x >> 6) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int2 wi = info[gw];
+    if (wi.x < 0) return;
+    assemble_body<T, P, FUEL>(prms[wi.x], wi.y);
+}
+
 template <typename T>
-static iga_status launch_t(const iga_plan *pl, int substep, const void *S, const void *F, void *R,
-                           void *RF, hipStream_t s)
+static void make_params(const iga_plan *pl, int substep, const void *S, const void *F, void *R,
+                        void *RF, AsmParams<T> &a)
 {
     const iga_plan_desc &d = pl->d;
     const int P = pl->P, Q = P + 1;
-    AsmParams<T> a;
     std::memset(&a, 0, sizeof a);
     a.S = static_cast<const T *>(S);
     a.F = static_cast<const T *>(F);
@@ -385,6 +403,15 @@ static iga_status launch_t(const iga_plan *pl, int substep, const void *S, const
     a.rows = pl->asm_rows;
     a.nstrips = (pl->Ny + (64 - P) - 1) / (64 - P);
     a.ntiles = (pl->Nx + a.rows - 1) / a.rows;
+}
+
+template <typename T>
+static iga_status launch_t(const iga_plan *pl, int substep, const void *S, const void *F, void *R,
+                           void *RF, hipStream_t s)
+{
+    AsmParams<T> a;
+    make_params<T>(pl, substep, S, F, R, RF, a);
+    const int P = pl->P;
     const int waves = a.nstrips * a.ntiles;
     const int blocks = (waves + 3) / 4;
     const bool fuel = RF != nullptr;
@@ -409,6 +436,55 @@ iga_status launch_assemble(const iga_plan *pl, int substep, const void *S, const
 {
     return pl->fp32 ? launch_t<float>(pl, substep, S, F, R, RF, s)
                     : launch_t<double>(pl, substep, S, F, R, RF, s);
+}
+
+template <typename T>
+static iga_status batch_t(const std::vector<iga_plan *> &pls, const std::vector<AsmArgs> &args,
+                          BatchLaunch &out)
+{
+    const int P = pls[0]->P;
+    const bool fuel = args[0].RF != nullptr;
+    std::vector<AsmParams<T>> prms(pls.size());
+    std::vector<int2> info;
+    for (size_t m = 0; m < pls.size(); ++m) {
+        if (pls[m]->P != P || pls[m]->fp32 != pls[0]->fp32 || (args[m].RF != nullptr) != fuel)
+            return fail(IGA_EINVAL, "assembly batch: members differ in degree, precision or fuel");
+        make_params<T>(pls[m], args[m].substep, args[m].T, args[m].fuel, args[m].R, args[m].RF,
+                       prms[m]);
+        const int waves = prms[m].nstrips * prms[m].ntiles;
+        for (int w = 0; w < waves; ++w) info.push_back(int2{(int)m, w});
+    }
+    while (info.size() % 4) info.push_back(int2{-1, 0});
+    const void *fn = nullptr;
+#define IGA_ASMB(P_, FU_) fn = reinterpret_cast<const void *>(k_assemble_batch<T, P_, FU_>)
+    if (P == 2) {
+        if (fuel) IGA_ASMB(2, true);
+        else IGA_ASMB(2, false);
+    } else if (P == 3) {
+        if (fuel) IGA_ASMB(3, true);
+        else IGA_ASMB(3, false);
+    } else {
+        return fail(IGA_EUNSUPPORTED, "degree not compiled");
+    }
+#undef IGA_ASMB
+    out.fn = fn;
+    out.nblk = (int)(info.size() / 4);
+    out.njobs = 1;
+    out.block = 256;
+    out.lds = 0;
+    IGA_HIP(out.prm.alloc(prms.size() * sizeof(AsmParams<T>)));
+    IGA_HIP(out.info.alloc(info.size() * sizeof(int2)));
+    IGA_HIP(hipMemcpy(out.prm.ptr, prms.data(), prms.size() * sizeof(AsmParams<T>),
+                      hipMemcpyHostToDevice));
+    IGA_HIP(hipMemcpy(out.info.ptr, info.data(), info.size() * sizeof(int2), hipMemcpyHostToDevice));
+    return IGA_OK;
+}
+
+iga_status build_assemble_batch(const std::vector<iga_plan *> &pls, const std::vector<AsmArgs> &args,
+                                BatchLaunch &out)
+{
+    if (pls.empty() || args.size() != pls.size()) return fail(IGA_EINVAL, "assembly batch: members");
+    return pls[0]->fp32 ? batch_t<float>(pls, args, out) : batch_t<double>(pls, args, out);
 }
 
 // ---------------------------------------------------------------------------

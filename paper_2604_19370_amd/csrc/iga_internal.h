@@ -36,6 +36,22 @@ struct DevBuf {
     DevBuf() = default;
     DevBuf(const DevBuf &) = delete;
     DevBuf &operator=(const DevBuf &) = delete;
+    DevBuf(DevBuf &&o) noexcept : ptr(o.ptr), bytes(o.bytes)
+    {
+        o.ptr = nullptr;
+        o.bytes = 0;
+    }
+    DevBuf &operator=(DevBuf &&o) noexcept
+    {
+        if (this != &o) {
+            release();
+            ptr = o.ptr;
+            bytes = o.bytes;
+            o.ptr = nullptr;
+            o.bytes = 0;
+        }
+        return *this;
+    }
     ~DevBuf() { release(); }
     hipError_t alloc(size_t n) {
         release();
@@ -171,11 +187,97 @@ struct SweepJob {
 iga_status launch_sweep(const iga_plan *pl, int dir, const SweepJob *jobs, int njobs,
                         hipStream_t s);
 int sweep_capacity(int m);           // smallest compiled register capacity >= m (0: none)
+
+// A prepared batched launch over ensemble members: kernel, per-member
+// parameter records and the per-workgroup (member, block) table on the device.
+struct BatchLaunch {
+    const void *fn = nullptr;
+    DevBuf prm, info;
+    int nblk = 0, njobs = 1, block = 256;
+    size_t lds = 0;
+};
+iga_status build_sweep_batch(const std::vector<iga_plan *> &pls, int dir,
+                             const std::vector<std::vector<SweepJob>> &jobs,
+                             std::vector<BatchLaunch> &out);
+// assembly of substep substeps[m] for member m: (T, fuel) -> (R, R_fuel or NULL)
+struct AsmArgs {
+    int substep;
+    const void *T, *fuel;
+    void *R, *RF;
+};
+iga_status build_assemble_batch(const std::vector<iga_plan *> &pls, const std::vector<AsmArgs> &args,
+                                BatchLaunch &out);
+iga_status launch_batch(const BatchLaunch &b, hipStream_t s);
 iga_status sweep_prepare(const iga_plan *pl, int dir);
 size_t sweep_lds_bytes(const iga_plan *pl, int dir, int lines, int wpl);
 
 // kernels (util)
 iga_status launch_nonfinite(const iga_plan *pl, const void *T, const void *fuel, int *flag,
                             hipStream_t s);
+
+// the launches of one step of a plan on fields (T, fuel) (api.cpp)
+struct StepPhases {
+    AsmArgs a1, a2;
+    std::vector<SweepJob> x1, y1, x2, y2;
+};
+void step_phases(const iga_plan *pl, void *T, void *fuel, StepPhases &sp);
+iga_status check_desc(const iga_plan_desc *d);
+iga_status check_field(const void *p, const char *name);
+
+// Capture `steps` repetitions of one_step(stream) into g on a private stream
+// (kernels only).
+template <typename F> iga_status capture_graph(GraphEntry &g, int64_t steps, F &&one_step)
+{
+    g.reset();
+    hipStream_t cs;
+    IGA_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+    hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) {
+        (void)hipStreamDestroy(cs);
+        return hip_fail(e, "hipStreamBeginCapture");
+    }
+    iga_status cst = IGA_OK;
+    for (int64_t k = 0; k < steps && !cst; ++k) cst = one_step(cs);
+    hipGraph_t graph = nullptr;
+    e = hipStreamEndCapture(cs, &graph);
+    (void)hipStreamDestroy(cs);
+    if (cst) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return cst;
+    }
+    if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+    hipGraphExec_t exec = nullptr;
+    e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        (void)hipGraphDestroy(graph);
+        return hip_fail(e, "hipGraphInstantiate");
+    }
+    g.graph = graph;
+    g.exec = exec;
+    g.steps = steps;
+    return IGA_OK;
+}
+
+// Time `reps` launches of fn between HIP events on s; returns ms per launch
+// (negative on failure).
+template <typename F> float time_launches(hipStream_t s, int reps, F &&fn)
+{
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess) return -1.f;
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return -1.f;
+    }
+    float ms = -1.f;
+    bool ok = fn() == IGA_OK;   // warm-up
+    ok = ok && hipEventRecord(e0, s) == hipSuccess;
+    for (int i = 0; i < reps && ok; ++i) ok = fn() == IGA_OK;
+    ok = ok && hipEventRecord(e1, s) == hipSuccess && hipEventSynchronize(e1) == hipSuccess;
+    if (ok && hipEventElapsedTime(&ms, e0, e1) == hipSuccess) ms /= reps;
+    else ms = -1.f;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return ms;
+}
 
 }  // namespace iga

@@ -60,13 +60,23 @@ iga_status sweep_prepare(const iga_plan *pl, int dir)
     return IGA_OK;
 }
 
-iga_status launch_sweep(const iga_plan *pl, int dir, const SweepJob *jobs, int njobs, hipStream_t s)
+static SweepBatchFn pick_batch_fn(bool fp32, int P, int mm, bool diry)
+{
+    if (fp32) {
+        if (P == 2) return pick_sweep_batch_f2(mm, diry);
+        if (P == 3) return pick_sweep_batch_f3(mm, diry);
+    } else {
+        if (P == 2) return pick_sweep_batch_d2(mm, diry);
+        if (P == 3) return pick_sweep_batch_d3(mm, diry);
+    }
+    return nullptr;
+}
+
+static iga_status build_params(const iga_plan *pl, int dir, const SweepJob *jobs, int njobs,
+                               SweepParams &prm)
 {
     if (njobs < 1 || njobs > MAXJOBS) return fail(IGA_EINVAL, "bad sweep job count");
     const Schedule &sc = pl->sched[dir];
-    SweepFn fn = pick_fn(pl->fp32, pl->P, sc.mm, dir == 1);
-    if (!fn) return fail(IGA_EUNSUPPORTED, "line-solve kernel not compiled for this schedule");
-    SweepParams prm;
     std::memset(&prm, 0, sizeof prm);
     for (int j = 0; j < njobs; ++j) {
         prm.jobs[j] = jobs[j];
@@ -88,11 +98,83 @@ iga_status launch_sweep(const iga_plan *pl, int dir, const SweepJob *jobs, int n
     prm.Ns = (int)stage_stride(prm.N, dir);
     prm.W = sc.lines;
     prm.WPL = sc.wpl;
+    prm.njobs = njobs;
+    return IGA_OK;
+}
+
+iga_status launch_sweep(const iga_plan *pl, int dir, const SweepJob *jobs, int njobs, hipStream_t s)
+{
+    const Schedule &sc = pl->sched[dir];
+    SweepFn fn = pick_fn(pl->fp32, pl->P, sc.mm, dir == 1);
+    if (!fn) return fail(IGA_EUNSUPPORTED, "line-solve kernel not compiled for this schedule");
+    SweepParams prm;
+    iga_status st = build_params(pl, dir, jobs, njobs, prm);
+    if (st) return st;
     const int nblk = (prm.nlines + sc.lines - 1) / sc.lines;
     const size_t lds = sweep_lds_bytes(pl, dir, sc.lines, sc.wpl);
     if (lds > 160 * 1024) return fail(IGA_EUNSUPPORTED, "line-solve tables do not fit in LDS");
     hipLaunchKernelGGL(fn, dim3(nblk, njobs), dim3(sc.lines * sc.wpl * 64), lds, s, prm);
     IGA_HIP(hipGetLastError());
+    return IGA_OK;
+}
+
+// Batched sweeps of one direction over several plans: members are grouped by
+// schedule (rows per lane, lines per workgroup, wavefronts per line), one
+// launch per group.
+iga_status build_sweep_batch(const std::vector<iga_plan *> &pls, int dir,
+                             const std::vector<std::vector<SweepJob>> &jobs,
+                             std::vector<BatchLaunch> &out)
+{
+    out.clear();
+    if (pls.empty() || jobs.size() != pls.size()) return fail(IGA_EINVAL, "sweep batch: members");
+    std::vector<int> done(pls.size(), 0);
+    for (size_t m0 = 0; m0 < pls.size(); ++m0) {
+        if (done[m0]) continue;
+        const Schedule key = pls[m0]->sched[dir];
+        std::vector<SweepParams> prms;
+        std::vector<int2> info;
+        int maxjobs = 1;
+        size_t lds = 0;
+        for (size_t m = m0; m < pls.size(); ++m) {
+            const Schedule &sc = pls[m]->sched[dir];
+            if (done[m] || sc.mm != key.mm || sc.lines != key.lines || sc.wpl != key.wpl) continue;
+            done[m] = 1;
+            SweepParams prm;
+            iga_status st = build_params(pls[m], dir, jobs[m].data(), (int)jobs[m].size(), prm);
+            if (st) return st;
+            const int nblk = (prm.nlines + sc.lines - 1) / sc.lines;
+            for (int b = 0; b < nblk; ++b) info.push_back(int2{(int)prms.size(), b});
+            prms.push_back(prm);
+            maxjobs = std::max(maxjobs, prm.njobs);
+            lds = std::max(lds, sweep_lds_bytes(pls[m], dir, sc.lines, sc.wpl));
+        }
+        if (lds > 160 * 1024) return fail(IGA_EUNSUPPORTED, "line-solve tables do not fit in LDS");
+        SweepBatchFn fn = pick_batch_fn(pls[m0]->fp32, pls[m0]->P, key.mm, dir == 1);
+        if (!fn) return fail(IGA_EUNSUPPORTED, "line-solve kernel not compiled for this schedule");
+        IGA_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(fn),
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
+        out.emplace_back();
+        BatchLaunch &bl = out.back();
+        bl.fn = reinterpret_cast<const void *>(fn);
+        bl.nblk = (int)info.size();
+        bl.njobs = maxjobs;
+        bl.block = key.lines * key.wpl * 64;
+        bl.lds = lds;
+        IGA_HIP(bl.prm.alloc(prms.size() * sizeof(SweepParams)));
+        IGA_HIP(bl.info.alloc(info.size() * sizeof(int2)));
+        IGA_HIP(hipMemcpy(bl.prm.ptr, prms.data(), prms.size() * sizeof(SweepParams),
+                          hipMemcpyHostToDevice));
+        IGA_HIP(hipMemcpy(bl.info.ptr, info.data(), info.size() * sizeof(int2),
+                          hipMemcpyHostToDevice));
+    }
+    return IGA_OK;
+}
+
+iga_status launch_batch(const BatchLaunch &b, hipStream_t s)
+{
+    void *prm = b.prm.ptr, *info = b.info.ptr;
+    void *args[] = {&prm, &info};
+    IGA_HIP(hipLaunchKernel(b.fn, dim3(b.nblk, b.njobs), dim3(b.block), args, b.lds, s));
     return IGA_OK;
 }
 

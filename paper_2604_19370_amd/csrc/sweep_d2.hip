@@ -3,4 +3,6 @@
 
 namespace iga {
 SweepFn pick_sweep_d2(int mm, bool diry) { return pick_mm<double, 2>(mm, diry); }
+SweepBatchFn pick_sweep_batch_d2(int mm, bool diry) { return pick_mm_batch<double, 2>(mm, diry); }
+
 }  // namespace iga

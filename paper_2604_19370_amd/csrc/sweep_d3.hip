@@ -3,4 +3,6 @@
 
 namespace iga {
 SweepFn pick_sweep_d3(int mm, bool diry) { return pick_mm<double, 3>(mm, diry); }
+SweepBatchFn pick_sweep_batch_d3(int mm, bool diry) { return pick_mm_batch<double, 3>(mm, diry); }
+
 }  // namespace iga

@@ -3,4 +3,6 @@
 
 namespace iga {
 SweepFn pick_sweep_f2(int mm, bool diry) { return pick_mm<float, 2>(mm, diry); }
+SweepBatchFn pick_sweep_batch_f2(int mm, bool diry) { return pick_mm_batch<float, 2>(mm, diry); }
+
 }  // namespace iga

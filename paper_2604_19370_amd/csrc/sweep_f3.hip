@@ -3,4 +3,6 @@
 
 namespace iga {
 SweepFn pick_sweep_f3(int mm, bool diry) { return pick_mm<float, 3>(mm, diry); }
+SweepBatchFn pick_sweep_batch_f3(int mm, bool diry) { return pick_mm_batch<float, 3>(mm, diry); }
+
 }  // namespace iga

@@ -57,6 +57,7 @@ struct SweepParams {
     int Ns;       // LDS stride between staged lines
     int W;        // lines per workgroup (power of two)
     int WPL;      // wavefronts per line (power of two)
+    int njobs;    // jobs in use
 };
 
 template <int P> struct RowStride {
@@ -363,14 +364,15 @@ template <typename T, int P, int MM> constexpr int sweep_max_threads()
     return (sizeof(T) == 8 && P == 3 && MM >= 12) ? 512 : 1024;
 }
 
+// One workgroup's work: W lines starting at line blk*W, job `jobi`.
 template <typename T, int P, int MM, bool DIRY>
-__global__ __launch_bounds__((sweep_max_threads<T, P, MM>())) void k_sweep(SweepParams prm)
+__device__ __forceinline__ void sweep_body(const SweepParams &prm, const int blk, const int jobi)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     constexpr int RS = RowStride<P>::RS;
     constexpr int PP = P * P;
     constexpr bool F32 = sizeof(T) == 4;
-    const SweepJob job = prm.jobs[blockIdx.y];
+    const SweepJob job = prm.jobs[jobi];
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -378,7 +380,6 @@ __global__ __launch_bounds__((sweep_max_threads<T, P, MM>())) void k_sweep(Sweep
     const int wlog = __builtin_ctz(W);
     const int rstep = blockDim.x >> wlog;
     const int N = prm.N, Ns = prm.Ns, ld = prm.ld;
-    const int blk = xcd_remap(blockIdx.x, gridDim.x);
     const int line0 = blk * W;
     const int nl = min(W, prm.nlines - line0);
     const int lw = wave / WPL;          // line of this wavefront within the workgroup
@@ -543,7 +544,28 @@ __global__ __launch_bounds__((sweep_max_threads<T, P, MM>())) void k_sweep(Sweep
     store_lines(static_cast<T *>(job.dst));
 }
 
+template <typename T, int P, int MM, bool DIRY>
+__global__ __launch_bounds__((sweep_max_threads<T, P, MM>())) void k_sweep(SweepParams prm)
+{
+    sweep_body<T, P, MM, DIRY>(prm, xcd_remap(blockIdx.x, gridDim.x), blockIdx.y);
+}
+
+// Batched launch over the members of an ensemble: workgroup b works block
+// info[b].y of member info[b].x (x < 0: no work), job blockIdx.y if the
+// member has that many jobs.
+template <typename T, int P, int MM, bool DIRY>
+__global__ __launch_bounds__((sweep_max_threads<T, P, MM>())) void k_sweep_batch(
+    const SweepParams *__restrict__ prms, const int2 *__restrict__ info)
+{
+    const int2 bi = info[xcd_remap(blockIdx.x, gridDim.x)];
+    if (bi.x < 0) return;
+    const SweepParams &prm = prms[bi.x];
+    if ((int)blockIdx.y >= prm.njobs) return;
+    sweep_body<T, P, MM, DIRY>(prm, bi.y, blockIdx.y);
+}
+
 using SweepFn = void (*)(SweepParams);
+using SweepBatchFn = void (*)(const SweepParams *, const int2 *);
 
 #define IGA_SWEEP_MMS(X) X(4) X(8) X(12) X(17)
 
@@ -556,9 +578,22 @@ template <typename T, int P> static SweepFn pick_mm(int mm, bool diry)
     return nullptr;
 }
 
+template <typename T, int P> static SweepBatchFn pick_mm_batch(int mm, bool diry)
+{
+#define IGA_CASE(MM_) \
+    if (mm == MM_) return diry ? k_sweep_batch<T, P, MM_, true> : k_sweep_batch<T, P, MM_, false>;
+    IGA_SWEEP_MMS(IGA_CASE)
+#undef IGA_CASE
+    return nullptr;
+}
+
 SweepFn pick_sweep_f2(int mm, bool diry);
 SweepFn pick_sweep_f3(int mm, bool diry);
 SweepFn pick_sweep_d2(int mm, bool diry);
 SweepFn pick_sweep_d3(int mm, bool diry);
+SweepBatchFn pick_sweep_batch_f2(int mm, bool diry);
+SweepBatchFn pick_sweep_batch_f3(int mm, bool diry);
+SweepBatchFn pick_sweep_batch_d2(int mm, bool diry);
+SweepBatchFn pick_sweep_batch_d3(int mm, bool diry);
 
 }  // namespace iga

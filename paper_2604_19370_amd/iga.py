@@ -23,7 +23,10 @@ WIND_CONST, WIND_SINCOS = 0, 1
 EXPORTED = ("iga_default_coeffs", "iga_plan_create", "iga_plan_destroy", "iga_plan_dims",
             "iga_factor_1d", "iga_assemble_rhs", "iga_line_solve", "iga_step", "iga_run",
             "iga_plan_schedule", "iga_plan_set_schedule", "iga_plan_set_assembly_rows",
-            "iga_plan_assembly_rows", "iga_autotune", "iga_last_error")
+            "iga_plan_assembly_rows", "iga_autotune", "iga_ensemble_create", "iga_ensemble_destroy",
+            "iga_ensemble_size", "iga_ensemble_launches", "iga_ensemble_step", "iga_ensemble_run",
+            "iga_ensemble_set_schedule", "iga_ensemble_set_assembly_rows", "iga_ensemble_autotune",
+            "iga_last_error")
 
 _COEFF_NAMES = ("c_adv", "c_diff", "c_react", "c_nld", "c_ign", "t_ig", "fuel_thr", "t_act",
                 "c_forcing", "c_rad", "fuel_rate")
@@ -81,6 +84,16 @@ def lib() -> ctypes.CDLL:
         L.iga_plan_assembly_rows.argtypes = [vp]
         L.iga_plan_assembly_rows.restype = i32
         L.iga_autotune.argtypes = [vp, vp, vp, i32, vp]
+        pp = ctypes.POINTER(vp)
+        L.iga_ensemble_create.argtypes = [ctypes.POINTER(PlanDesc), i32, ctypes.POINTER(vp)]
+        L.iga_ensemble_destroy.argtypes = [vp]
+        L.iga_ensemble_size.argtypes = [vp, ctypes.POINTER(i32)]
+        L.iga_ensemble_launches.argtypes = [vp, ctypes.POINTER(i32)]
+        L.iga_ensemble_step.argtypes = [vp, pp, pp, vp]
+        L.iga_ensemble_run.argtypes = [vp, pp, pp, i64, vp]
+        L.iga_ensemble_set_schedule.argtypes = [vp, i32, i32, i32]
+        L.iga_ensemble_set_assembly_rows.argtypes = [vp, i32]
+        L.iga_ensemble_autotune.argtypes = [vp, pp, pp, i32, vp]
         L.iga_last_error.argtypes = []
         L.iga_last_error.restype = ctypes.c_char_p
         for name in EXPORTED[1:-1]:
@@ -231,3 +244,82 @@ class Plan:
 
     def set_assembly_rows(self, rows):
         _check(lib().iga_plan_set_assembly_rows(self._h, int(rows)), "iga_plan_set_assembly_rows")
+
+
+class Ensemble:
+    """An iga_ensemble: member plans stepped together by batched launches.
+
+    ``descs`` is a list of PlanDesc (same degree and precision).  Fields are
+    passed as lists of tensors, member m's of shape (Nx_m, Ny_m)."""
+
+    def __init__(self, descs):
+        n = len(descs)
+        arr = (PlanDesc * n)(*descs)
+        h = ctypes.c_void_p()
+        _check(lib().iga_ensemble_create(arr, n, ctypes.byref(h)), "iga_ensemble_create")
+        self._h = h
+        self.descs = list(descs)
+        self.shapes = [(d.nel_x + d.p, d.nel_y + d.p) for d in descs]
+        self.fp32 = descs[0].precision == FP32_REFINE
+
+    @classmethod
+    def from_scenarios(cls, scs, precision="fp32", coeffs=None) -> "Ensemble":
+        return cls([make_desc(sc.nel_x, sc.nel_y, sc.p, sc.len_x, sc.len_y, sc.dt, sc.scheme,
+                              precision=precision, wind=sc.wind_dict(), coeffs=coeffs)
+                    for sc in scs])
+
+    @property
+    def dtype(self):
+        import torch
+        return torch.float32 if self.fp32 else torch.float64
+
+    def __len__(self):
+        return len(self.shapes)
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().iga_ensemble_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _fields(self, ts, name):
+        if len(ts) != len(self.shapes):
+            raise ValueError(f"{name}: expected {len(self.shapes)} tensors")
+        for m, t in enumerate(ts):
+            if t.dtype != self.dtype or not t.is_contiguous() or tuple(t.shape) != self.shapes[m]:
+                raise ValueError(f"{name}[{m}]: expected contiguous {self.dtype} tensor of shape "
+                                 f"{self.shapes[m]}, got {t.dtype} {tuple(t.shape)}")
+            if t.device.type != "cuda":
+                raise ValueError(f"{name}[{m}] must be on the GPU")
+        return (ctypes.c_void_p * len(ts))(*[t.data_ptr() for t in ts])
+
+    @property
+    def launches_per_step(self) -> int:
+        v = ctypes.c_int32()
+        _check(lib().iga_ensemble_launches(self._h, ctypes.byref(v)), "iga_ensemble_launches")
+        return v.value
+
+    def step(self, Ts, Fs, stream=None):
+        _check(lib().iga_ensemble_step(self._h, self._fields(Ts, "T"), self._fields(Fs, "fuel"),
+                                       _stream(stream)), "iga_ensemble_step")
+
+    def run(self, Ts, Fs, nsteps, stream=None):
+        _check(lib().iga_ensemble_run(self._h, self._fields(Ts, "T"), self._fields(Fs, "fuel"),
+                                      int(nsteps), _stream(stream)), "iga_ensemble_run")
+
+    def set_schedule(self, dir, lines, waves_per_line=1):
+        _check(lib().iga_ensemble_set_schedule(self._h, int(dir), int(lines), int(waves_per_line)),
+               "iga_ensemble_set_schedule")
+
+    def set_assembly_rows(self, rows):
+        _check(lib().iga_ensemble_set_assembly_rows(self._h, int(rows)),
+               "iga_ensemble_set_assembly_rows")
+
+    def autotune(self, Ts, Fs, reps=10, stream=None):
+        _check(lib().iga_ensemble_autotune(self._h, self._fields(Ts, "T"), self._fields(Fs, "fuel"),
+                                           int(reps), _stream(stream)), "iga_ensemble_autotune")

@@ -59,3 +59,28 @@ def test_null_arguments_are_rejected():
     bad_wind.wind.kind = 5
     h = ctypes.c_void_p()
     assert L.iga_plan_create(ctypes.byref(bad_wind), ctypes.byref(h)) == iga.EINVAL
+
+
+def test_ensemble_arguments_are_checked_before_any_device_work():
+    L = iga.lib()
+    h = ctypes.c_void_p()
+    good = iga.make_desc(16, 16, 2, 16.0, 16.0, 1e-3, "pr")
+    cubic = iga.make_desc(16, 16, 3, 16.0, 16.0, 1e-3, "pr")
+    f32 = iga.make_desc(16, 16, 2, 16.0, 16.0, 1e-3, "pr", precision="fp32")
+    bad = iga.make_desc(16, 16, 2, 16.0, -1.0, 1e-3, "pr")
+    assert L.iga_ensemble_create(None, 1, ctypes.byref(h)) == iga.EINVAL
+    assert L.iga_ensemble_create((iga.PlanDesc * 1)(good), 0, ctypes.byref(h)) == iga.EINVAL
+    assert L.iga_ensemble_create((iga.PlanDesc * 1)(good), 1, None) == iga.EINVAL
+    for other in (cubic, f32, bad):
+        arr = (iga.PlanDesc * 2)(good, other)
+        assert L.iga_ensemble_create(arr, 2, ctypes.byref(h)) == iga.EINVAL
+        assert not h.value
+    assert L.iga_ensemble_destroy(None) == iga.OK
+    assert L.iga_ensemble_step(None, None, None, None) == iga.EINVAL
+    assert L.iga_ensemble_run(None, None, None, 1, None) == iga.EINVAL
+    assert L.iga_ensemble_autotune(None, None, None, 1, None) == iga.EINVAL
+    assert L.iga_ensemble_set_schedule(None, 0, 1, 1) == iga.EINVAL
+    assert L.iga_ensemble_set_assembly_rows(None, 4) == iga.EINVAL
+    n = ctypes.c_int32()
+    assert L.iga_ensemble_size(None, ctypes.byref(n)) == iga.EINVAL
+    assert L.iga_ensemble_launches(None, ctypes.byref(n)) == iga.EINVAL

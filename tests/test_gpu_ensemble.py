@@ -1,0 +1,203 @@
+"""Ensembles: batched launches over members of uneven sizes, schemes, time
+steps and winds, through the C ABI.
+
+- Small mixed ensembles (several tiles and ragged tails, both schemes, the
+  minimum mesh), for each degree and precision: every member equals its own
+  plan's result under the same line-solve schedule up to rounding (the
+  batched kernels are separately compiled code; FP64 1e-13, FP32 1e-6
+  relative), and the oracle per step (FP64 1e-12; FP32+refine 1e-6 away from
+  ignition decisions within float rounding of a threshold).
+- Graph-replayed runs equal eager steps bitwise; autotuning keeps parity; the
+  launch count per step does not grow with the member count.
+- The 64-member uneven ensemble (256^2 .. 1024^2, p = 2) and the 16-member
+  2048^2 cubic ensembles (PR and Strang-CN), FP32+refine: one step of every
+  (64-member) or of sampled (cubic) members against the oracle.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2604_19370_amd import iga, inputs
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+AMB_DT, AMB_DF, MASK_RADIUS = 0.01, 1e-5, 12
+
+
+def dev(a, dtype):
+    return torch.tensor(np.ascontiguousarray(a), dtype=dtype, device="cuda")
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.double().cpu().numpy()
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def masked_rel(gpu, ref, flags, p):
+    """Relative L2 over dofs farther than MASK_RADIUS elements from elements
+    whose ignition decision is ambiguous in float, and the largest difference
+    inside."""
+    from scipy.ndimage import maximum_filter
+    near = np.zeros(ref.shape, dtype=bool)
+    ex, ey = np.nonzero(flags)
+    for a in range(p + 1):
+        for b in range(p + 1):
+            near[ex + a, ey + b] = True
+    if near.any():
+        near = maximum_filter(near, size=2 * MASK_RADIUS + 1)
+    diff = gpu - ref
+    outside = float(np.linalg.norm(diff[~near]) / np.linalg.norm(ref))
+    inside = float(np.abs(diff[near]).max()) if near.any() else 0.0
+    return outside, inside
+
+
+def members(p):
+    if p == 2:
+        return [inputs.small_case(11, 37, 29, 2, "pr"),
+                inputs.small_case(12, 29, 61, 2, "strang", dt=5e-4),
+                inputs.small_case(13, 130, 70, 2, "strang"),
+                inputs.small_case(14, 5, 5, 2, "pr"),
+                inputs.small_case(15, 300, 200, 2, "strang",
+                                  wind=inputs.Wind("const", 1.2, -0.4)),
+                inputs.small_case(16, 64, 64, 2, "pr")]
+    return [inputs.small_case(21, 45, 33, 3, "pr"),
+            inputs.small_case(22, 71, 40, 3, "strang"),
+            inputs.small_case(23, 7, 9, 3, "strang"),
+            inputs.small_case(24, 200, 150, 3, "pr", dt=5e-4)]
+
+
+def fields(ens, scs):
+    Ts = [dev(sc.T0, ens.dtype) for sc in scs]
+    Fs = [dev(sc.fuel0, ens.dtype) for sc in scs]
+    return Ts, Fs
+
+
+def check_vs_oracle(sc, T, F, Tprev, Fprev, precision):
+    od = oracle.desc_from_scenario(sc)
+    if precision == "fp64":
+        To, Fo = oracle.step(od, Tprev, Fprev)
+        eT, eF = rel(T, To), rel(F, Fo)
+        assert eT < 1e-12 and eF < 1e-12, (sc.name, eT, eF)
+        return max(eT, eF)
+    To, Fo, fl = oracle.step_flagged(od, Tprev, Fprev, AMB_DT, AMB_DF)
+    eT, iT = masked_rel(T, To, fl, sc.p)
+    eF, iF = masked_rel(F, Fo, fl, sc.p)
+    assert eT < 1e-6 and eF < 1e-6, (sc.name, eT, eF)
+    assert iT < 50.0 and iF < 0.05, (sc.name, iT, iF)
+    return max(eT, eF)
+
+
+@pytest.mark.parametrize("p", [2, 3])
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_members_match_own_plans_and_oracle(p, precision):
+    scs = members(p)
+    print(f"ensemble p{p} {precision}: {[sc.name for sc in scs]}", flush=True)
+    ens = iga.Ensemble.from_scenarios(scs, precision=precision)
+    Ts, Fs = fields(ens, scs)
+    plans = []
+    for sc in scs:
+        pl = iga.Plan.from_scenario(sc, precision=precision)
+        pl.factor()
+        pl.set_schedule(0, 4, 0)   # the ensemble's default schedule
+        pl.set_schedule(1, 2, 0)
+        plans.append(pl)
+    Tp, Fp = fields(ens, scs)
+    worst = 0.0
+    for k in range(3):
+        prev = [(host(T), host(F)) for T, F in zip(Ts, Fs)]
+        ens.step(Ts, Fs)
+        for m, pl in enumerate(plans):
+            pl.step(Tp[m], Fp[m])
+        for m, sc in enumerate(scs):
+            T, F = host(Ts[m]), host(Fs[m])
+            tol = 1e-13 if precision == "fp64" else 1e-6
+            dT, dF = rel(T, host(Tp[m])), rel(F, host(Fp[m]))
+            assert dT < tol and dF < tol, f"member {m} vs its own plan at step {k}: {dT}, {dF}"
+            worst = max(worst, check_vs_oracle(sc, T, F, prev[m][0], prev[m][1], precision))
+    print(f"worst per-step error against the oracle: {worst:.3e}", flush=True)
+    for pl in plans:
+        pl.close()
+    ens.close()
+
+
+def test_run_graph_equals_eager_steps():
+    scs = members(2)
+    ens = iga.Ensemble.from_scenarios(scs, precision="fp32")
+    Ta, Fa = fields(ens, scs)
+    Tb, Fb = fields(ens, scs)
+    for _ in range(5):
+        ens.step(Ta, Fa)
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        ens.run(Tb, Fb, 5, stream)
+    torch.cuda.synchronize()
+    for m in range(len(scs)):
+        assert torch.equal(Ta[m], Tb[m]) and torch.equal(Fa[m], Fb[m])
+    # replays after re-binding other buffers still agree
+    with torch.cuda.stream(stream):
+        ens.run(Ta, Fa, 3, stream)
+        ens.run(Tb, Fb, 3, stream)
+    torch.cuda.synchronize()
+    for m in range(len(scs)):
+        assert torch.equal(Ta[m], Tb[m]) and torch.equal(Fa[m], Fb[m])
+    ens.close()
+
+
+def test_autotune_keeps_parity_and_launch_count():
+    scs = members(2)
+    ens = iga.Ensemble.from_scenarios(scs, precision="fp32")
+    Ts, Fs = fields(ens, scs)
+    n0 = ens.launches_per_step
+    ens.autotune(Ts, Fs, reps=2)
+    n1 = ens.launches_per_step
+    print(f"launches per step: default {n0}, tuned {n1}", flush=True)
+    assert 6 <= n0 <= 2 + 4 * 4 and 6 <= n1 <= 2 + 4 * 4
+    for k in range(2):
+        prev = [(host(T), host(F)) for T, F in zip(Ts, Fs)]
+        ens.step(Ts, Fs)
+        for m, sc in enumerate(scs):
+            check_vs_oracle(sc, host(Ts[m]), host(Fs[m]), prev[m][0], prev[m][1], "fp32")
+    ens.close()
+
+
+def test_sixty_four_uneven_members_one_step():
+    scs = inputs.mixed_ensemble(64)
+    sizes = sorted({sc.nel_x for sc in scs})
+    print(f"64 members, sizes {sizes}, {sum(sc.ndof for sc in scs)} dofs", flush=True)
+    ens = iga.Ensemble.from_scenarios(scs, precision="fp32")
+    Ts, Fs = fields(ens, scs)
+    ens.autotune(Ts, Fs, reps=2)
+    print(f"launches per step {ens.launches_per_step}", flush=True)
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        ens.run(Ts, Fs, 1, stream)
+    torch.cuda.synchronize()
+    worst = 0.0
+    for m, sc in enumerate(scs):
+        worst = max(worst, check_vs_oracle(sc, host(Ts[m]), host(Fs[m]), sc.T0, sc.fuel0, "fp32"))
+    print(f"worst member error after one step: {worst:.3e}", flush=True)
+    ens.close()
+
+
+@pytest.mark.parametrize("scheme", ["pr", "strang"])
+def test_sixteen_cubic_2048_members_one_step(scheme):
+    scs = inputs.cubic_ensemble(16, scheme=scheme)
+    print(f"16 cubic members 2048^2 {scheme}", flush=True)
+    ens = iga.Ensemble.from_scenarios(scs, precision="fp32")
+    Ts, Fs = fields(ens, scs)
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        ens.run(Ts, Fs, 1, stream)
+    torch.cuda.synchronize()
+    for m in (0, 15):
+        e = check_vs_oracle(scs[m], host(Ts[m]), host(Fs[m]), scs[m].T0, scs[m].fuel0, "fp32")
+        print(f"member {m}: {e:.3e}", flush=True)
+    for T in Ts:
+        assert torch.isfinite(T).all()
+    ens.close()
