@@ -43,6 +43,8 @@ def parse():
                          "copy kernel of known size (for profiler runs)")
     ap.add_argument("--schedule", type=str, default=None,
                     help="fixed schedule 'xlines,xwpl,ylines,ywpl,asmrows' instead of autotuning")
+    ap.add_argument("--no-ensembles", action="store_true",
+                    help="skip the ensemble workloads (64 uneven members; 16 cubic 2048^2 members)")
     return ap.parse_args()
 
 
@@ -197,6 +199,57 @@ def apply_schedule(pl, spec):
     pl.set_assembly_rows(ar)
 
 
+def ensemble_throughput(scs, steps, torch, iga):
+    """DOF-steps/s of an FP32+refine ensemble: autotuned, graph captured
+    (untimed), then `steps` graph-replayed steps between HIP events."""
+    ens = iga.Ensemble.from_scenarios(scs, precision="fp32")
+    Ts = [torch.tensor(sc.T0, dtype=torch.float32, device="cuda") for sc in scs]
+    Fs = [torch.tensor(sc.fuel0, dtype=torch.float32, device="cuda") for sc in scs]
+    T0 = [t.clone() for t in Ts]
+    F0 = [f.clone() for f in Fs]
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        ens.autotune(Ts, Fs, reps=3, stream=stream)
+        ens.run(Ts, Fs, steps, stream)             # captures the graphs
+        for t, t0, f, f0 in zip(Ts, T0, Fs, F0):
+            t.copy_(t0)
+            f.copy_(f0)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    with torch.cuda.stream(stream):
+        t0 = time.perf_counter()
+        e0.record(stream)
+        ens.run(Ts, Fs, steps, stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+    ok = all(bool(torch.isfinite(t).all()) for t in Ts)
+    dofs = sum(sc.ndof for sc in scs)
+    bpd = 60 if scs[0].scheme == "strang" else 52
+    out = {"members": len(scs), "dofs": dofs, "steps": steps, "p": scs[0].p,
+           "scheme": scs[0].scheme, "value": round(dofs * steps / wall, 1),
+           "unit": "DOF-steps/s", "ms_per_step": round(wall / steps * 1e3, 4),
+           "event_ms_per_step": round(e0.elapsed_time(e1) / steps, 4),
+           "launches_per_step": ens.launches_per_step,
+           "step_hbm_frac": round(dofs * steps / wall * bpd / (HBM_PEAK_GBS * 1e9), 4),
+           "finite": ok}
+    ens.close()
+    return out
+
+
+def ensembles(torch, iga, inputs):
+    res = {}
+    scs = inputs.mixed_ensemble(64)
+    res["mixed64_256to1024_p2_strang"] = ensemble_throughput(scs, 300, torch, iga)
+    del scs
+    cubic = inputs.cubic_ensemble(16, scheme="strang")
+    res["cubic16_2048_p3_strang"] = ensemble_throughput(cubic, 500, torch, iga)
+    for sc in cubic:
+        sc.scheme = "pr"
+    res["cubic16_2048_p3_pr"] = ensemble_throughput(cubic, 500, torch, iga)
+    return res
+
+
 def cpu_baseline(sc, budget_s):
     import oracle
     d = oracle.desc_from_scenario(sc)
@@ -289,6 +342,8 @@ def main():
         "roofline": roof,
         "schedules": res["fp32"]["sched"],
     }
+    if not args.no_ensembles:
+        line["ensembles"] = ensembles(torch, iga, inputs)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(sc, args.cpu_seconds)
     print(json.dumps(line), flush=True)
