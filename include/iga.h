@@ -177,13 +177,31 @@ iga_status iga_plan_schedule(const iga_plan *plan, int32_t dir, int32_t *lines,
                              int32_t *waves_per_line, int32_t *rows_per_lane,
                              int32_t *table_rows);
 
-/* Choose the line-solve schedule of direction dir: lines in {1, 2, 4, 8, 16}
- * lines per workgroup, waves_per_line in {1, 2, 4, 8} (0: the fewest that fit
- * the register budget), lines * waves_per_line <= 16.  IGA_EUNSUPPORTED if the
- * schedule does not fit the register or LDS budget for this line length; the
- * previous schedule is kept. */
+/* Choose an exact (chunk-scan) line-solve schedule of direction dir: lines
+ * in {1, 2, 4, 8, 16} lines per workgroup, waves_per_line in {1, 2, 4, 8} (0:
+ * the fewest that fit the register budget), lines * waves_per_line <= 16.
+ * IGA_EUNSUPPORTED if the schedule does not fit the register or LDS budget
+ * for this line length; the previous schedule is kept. */
 iga_status iga_plan_set_schedule(iga_plan *plan, int32_t dir, int32_t lines,
                                  int32_t waves_per_line);
+
+/* Windowed line solves of direction dir (the default after iga_factor_1d
+ * wherever the operators allow them).  Each lane restarts forward and backward
+ * substitution from a zero state `warmup` rows outside its chunk of
+ * rows_per_lane rows; the plan chooses warmup from the factors so that the
+ * restart changes the result by less than 2^-30 (FP32 plans, before the FP64
+ * refinement) or 2^-55 (FP64 plans) relative to the state, and refuses
+ * (IGA_EUNSUPPORTED) operators that would need more than 96 rows.
+ * rows_per_lane in {9, 13, 17, 25, 33} (0: 17); lines in {1, 2, 4, 8, 16}.
+ * Must follow iga_factor_1d; on failure the previous schedule is kept. */
+iga_status iga_plan_set_window_schedule(iga_plan *plan, int32_t dir, int32_t lines,
+                                        int32_t rows_per_lane);
+
+/* Solver of direction dir: *windowed = 1 for windowed solves, 0 for the exact
+ * chunk scan of iga_plan_set_schedule; *warmup = the windowed warm-up rows
+ * (0 if windowed solves are not possible or before factorisation).  Either
+ * pointer may be NULL. */
+iga_status iga_plan_solver(const iga_plan *plan, int32_t dir, int32_t *windowed, int32_t *warmup);
 
 /* Assembly schedule: element rows marched per wavefront (>= 1). */
 iga_status iga_plan_set_assembly_rows(iga_plan *plan, int32_t rows);
@@ -191,8 +209,8 @@ int32_t iga_plan_assembly_rows(const iga_plan *plan);
 
 /* Autotuner: times, with HIP events on `stream`, the assembly of the first
  * substep for several element-row tiles and the line solves of each direction
- * for every workgroup width, on the plan's scratch buffers (T and fuel are
- * only read), and keeps the fastest of each.  Synchronises `stream`; must
+ * for every windowed and exact schedule that fits, on the plan's scratch
+ * buffers (T and fuel are only read), and keeps the fastest of each.  Synchronises `stream`; must
  * follow iga_factor_1d.  reps >= 1 launches per candidate. */
 iga_status iga_autotune(iga_plan *plan, const void *T, const void *fuel, int32_t reps,
                         void *stream);
@@ -236,12 +254,17 @@ iga_status iga_ensemble_step(iga_ensemble *ens, void *const *T, void *const *fue
 iga_status iga_ensemble_run(iga_ensemble *ens, void *const *T, void *const *fuel, int64_t nsteps,
                             void *stream);
 
-/* Line-solve schedule of direction dir for every member: `lines` per
- * workgroup, at least waves_per_line wavefronts per line (more for members
- * whose lines need them).  On IGA_EUNSUPPORTED the previous schedules are
- * restored. */
+/* Exact (chunk-scan) line-solve schedule of direction dir for every member:
+ * `lines` per workgroup, at least waves_per_line wavefronts per line (more
+ * for members whose lines need them).  On IGA_EUNSUPPORTED the previous
+ * schedules are restored. */
 iga_status iga_ensemble_set_schedule(iga_ensemble *ens, int32_t dir, int32_t lines,
                                      int32_t waves_per_line);
+/* Windowed line solves (as iga_plan_set_window_schedule) on every member
+ * that allows them, the exact schedule with the same lines elsewhere.  The
+ * default after iga_ensemble_create is (4, 17) along x and (2, 17) along y. */
+iga_status iga_ensemble_set_window_schedule(iga_ensemble *ens, int32_t dir, int32_t lines,
+                                            int32_t rows_per_lane);
 iga_status iga_ensemble_set_assembly_rows(iga_ensemble *ens, int32_t rows);
 
 /* Autotuner of the batched launches: element-row tiles of the assembly, and

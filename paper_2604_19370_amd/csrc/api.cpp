@@ -78,14 +78,17 @@ void step_phases(const iga_plan *pl, void *T, void *fuel, StepPhases &sp)
     const int add = pl->delta ? 1 : 0;
     const bool pr = pl->d.scheme == IGA_PR;
     // substep 1 (PR: x implicit; Strang: S1) + the fuel right-hand side
+    // FP32 plans: the fuel increment vanishes exactly outside the burning
+    // region, and so do the windowed solves of it; those line blocks are skipped
+    const int zs = pl->delta ? 1 : 0;
     sp.a1 = AsmArgs{0, T, fuel, R, RF};
-    sp.x1 = {{R, R, OP_AX, -1, -1, nullptr, 0}, {RF, RF, OP_MX, -1, -1, nullptr, 0}};
+    sp.x1 = {{R, R, OP_AX, -1, -1, nullptr, 0}, {RF, RF, OP_MX, -1, -1, nullptr, 0, zs}};
     if (pr) {
         sp.y1 = {{R, T, OP_MY, -1, -1, bT, 0}};
         // substep 2: y implicit
         sp.a2 = AsmArgs{1, T, fuel, R, nullptr};
         sp.x2 = {{R, R, OP_MX, -1, -1, nullptr, 0}};
-        sp.y2 = {{R, T, OP_AY, -1, -1, bT, 0}, {RF, fuel, OP_MY, -1, -1, bF, 0}};
+        sp.y2 = {{R, T, OP_AY, -1, -1, bT, 0}, {RF, fuel, OP_MY, -1, -1, bF, 0, zs}};
     } else {
         // S1's y solve fused with S2: T** = (A^y)^{-1} B^y T* along y, with
         // T* = (M^y)^{-1} R (+ T^n in increment form)
@@ -93,7 +96,7 @@ void step_phases(const iga_plan *pl, void *T, void *fuel, StepPhases &sp)
         // S3
         sp.a2 = AsmArgs{2, T, fuel, R, nullptr};
         sp.x2 = {{R, R, OP_AX, -1, -1, nullptr, 0}};
-        sp.y2 = {{R, T, OP_MY, -1, -1, bT, 0}, {RF, fuel, OP_MY, -1, -1, bF, 0}};
+        sp.y2 = {{R, T, OP_MY, -1, -1, bT, 0}, {RF, fuel, OP_MY, -1, -1, bF, 0, zs}};
     }
 }
 
@@ -201,10 +204,14 @@ iga_status iga_factor_1d(iga_plan *plan, void *stream)
     if (!plan) return fail(IGA_EINVAL, "plan is NULL");
     iga_status st = launch_factor(plan, static_cast<hipStream_t>(stream));
     if (st) return st;
-    // the tables are known now: make sure each schedule still fits LDS
-    for (int dir = 0; dir < 2; ++dir)
-        if (sweep_lds_bytes(plan, dir, plan->sched[dir].lines, plan->sched[dir].wpl) > 160 * 1024)
-            if ((st = choose_schedule(plan, dir, 0, plan->sched[dir].wpl))) return st;
+    // the tables are known now: windowed solves where the operators decay
+    // fast enough, else an exact schedule that fits LDS
+    for (int dir = 0; dir < 2; ++dir) {
+        if (choose_window_schedule(plan, dir, 0, 0) == IGA_OK) continue;
+        (void)hipGetLastError();   // the fallback below is deliberate
+        if ((st = choose_schedule(plan, dir, 0, 0))) return st;
+    }
+    set_error("");
     plan->factored = true;
     plan->graph.reset();
     return IGA_OK;
@@ -330,6 +337,29 @@ iga_status iga_plan_set_schedule(iga_plan *plan, int32_t dir, int32_t lines, int
     return IGA_OK;
 }
 
+iga_status iga_plan_set_window_schedule(iga_plan *plan, int32_t dir, int32_t lines,
+                                       int32_t rows_per_lane)
+{
+    if (!plan) return fail(IGA_EINVAL, "plan is NULL");
+    if (dir != 0 && dir != 1) return fail(IGA_EINVAL, "dir must be 0 or 1");
+    if (lines != 1 && lines != 2 && lines != 4 && lines != 8 && lines != 16)
+        return fail(IGA_EINVAL, "lines must be 1, 2, 4, 8 or 16");
+    if (!plan->factored) return fail(IGA_ESTATE, "iga_factor_1d has not been called");
+    iga_status st = choose_window_schedule(plan, dir, lines, rows_per_lane);
+    if (st) return st;
+    plan->graph.reset();
+    return IGA_OK;
+}
+
+iga_status iga_plan_solver(const iga_plan *plan, int32_t dir, int32_t *windowed, int32_t *warmup)
+{
+    if (!plan) return fail(IGA_EINVAL, "plan is NULL");
+    if (dir != 0 && dir != 1) return fail(IGA_EINVAL, "dir must be 0 or 1");
+    if (windowed) *windowed = plan->sched[dir].win;
+    if (warmup) *warmup = plan->factored ? warmup_rows(plan, dir) : 0;
+    return IGA_OK;
+}
+
 iga_status iga_plan_set_assembly_rows(iga_plan *plan, int32_t rows)
 {
     if (!plan) return fail(IGA_EINVAL, "plan is NULL");
@@ -386,17 +416,31 @@ iga_status iga_autotune(iga_plan *plan, const void *T, const void *fuel, int32_t
         const Schedule keep = plan->sched[dir];
         Schedule best = keep;
         float best_ms = 1e30f;
-        const int wmin = keep.wpl;
+        auto consider = [&] {
+            float ms = time_launches(s, reps, [&] { return launch_sweep(plan, dir, jobs, nj, s); });
+            if (ms >= 0 && ms < best_ms) {
+                best_ms = ms;
+                best = plan->sched[dir];
+            }
+        };
+        // windowed solves (where the operators decay fast enough)
+        for (int mm : {9, 13, 17, 25, 33})
+            for (int w : {1, 2, 4, 8, 16})
+                if (choose_window_schedule(plan, dir, w, mm) == IGA_OK) consider();
+        // exact chunk-scan solves
+        int wmin = 1;
+        while (wmin < 8 && choose_schedule(plan, dir, 1, wmin) != IGA_OK) wmin *= 2;
         for (int wpl : {wmin, 2 * wmin, 4 * wmin}) {
             if (wpl > 8) continue;
             for (int w : {1, 2, 4, 8, 16}) {
                 if (w * wpl > 16) continue;
                 if (choose_schedule(plan, dir, w, wpl) != IGA_OK) continue;
-                float ms = time_launches(s, reps, [&] { return launch_sweep(plan, dir, jobs, nj, s); });
-                if (ms >= 0 && ms < best_ms) { best_ms = ms; best = plan->sched[dir]; }
+                consider();
             }
         }
-        if ((st = choose_schedule(plan, dir, best.lines, best.wpl))) return st;
+        if (best.win) st = choose_window_schedule(plan, dir, best.lines, best.mm);
+        else st = choose_schedule(plan, dir, best.lines, best.wpl);
+        if (st) return st;
     }
     IGA_HIP(hipStreamSynchronize(s));
     plan->graph.reset();

@@ -113,6 +113,23 @@ iga_status set_schedule_all(iga_ensemble *e, int dir, int lines, int wpl)
     return IGA_OK;
 }
 
+// windowed schedule of one direction on every member (`lines` lines per
+// workgroup, mm rows per lane); members whose operators do not allow it get
+// the exact schedule with the same lines and the fewest waves per line
+iga_status set_window_all(iga_ensemble *e, int dir, int lines, int mm)
+{
+    for (iga_plan *pl : e->plans) {
+        if (choose_window_schedule(pl, dir, lines, mm) == IGA_OK) continue;
+        (void)hipGetLastError();   // the fallback below is deliberate
+        iga_status st = IGA_EUNSUPPORTED;
+        for (int w = 1; w <= 8 && st; w *= 2) st = choose_schedule(pl, dir, lines, w);
+        if (st) return st;
+    }
+    set_error("");
+    e->unbind();
+    return IGA_OK;
+}
+
 int groups(const iga_ensemble *e, int dir)
 {
     std::vector<Schedule> seen;
@@ -120,7 +137,7 @@ int groups(const iga_ensemble *e, int dir)
         const Schedule &s = pl->sched[dir];
         bool found = false;
         for (const Schedule &t : seen)
-            found = found || (t.mm == s.mm && t.lines == s.lines && t.wpl == s.wpl);
+            found = found || (t.mm == s.mm && t.lines == s.lines && t.wpl == s.wpl && t.win == s.win);
         if (!found) seen.push_back(s);
     }
     return (int)seen.size();
@@ -156,8 +173,8 @@ iga_status iga_ensemble_create(const iga_plan_desc *members, int32_t n, iga_ense
         e->plans.push_back(pl);
     }
     // one schedule per direction for all members, so that members of equal
-    // rows-per-lane share a launch
-    if ((st = set_schedule_all(e, 0, 4, 1)) || (st = set_schedule_all(e, 1, 2, 1))) {
+    // line-solve shape share a launch
+    if ((st = set_window_all(e, 0, 4, 17)) || (st = set_window_all(e, 1, 2, 17))) {
         delete e;
         return st;
     }
@@ -227,8 +244,30 @@ iga_status iga_ensemble_set_schedule(iga_ensemble *ens, int32_t dir, int32_t lin
     for (iga_plan *pl : ens->plans) keep.push_back(pl->sched[dir]);
     iga_status st = set_schedule_all(ens, dir, lines, waves_per_line);
     if (st) {
-        for (size_t m = 0; m < ens->plans.size(); ++m)
-            (void)choose_schedule(ens->plans[m], dir, keep[m].lines, keep[m].wpl);
+        for (size_t m = 0; m < ens->plans.size(); ++m) {
+            if (keep[m].win) (void)choose_window_schedule(ens->plans[m], dir, keep[m].lines, keep[m].mm);
+            else (void)choose_schedule(ens->plans[m], dir, keep[m].lines, keep[m].wpl);
+        }
+        ens->unbind();
+    }
+    return st;
+}
+
+iga_status iga_ensemble_set_window_schedule(iga_ensemble *ens, int32_t dir, int32_t lines,
+                                            int32_t rows_per_lane)
+{
+    if (!ens) return fail(IGA_EINVAL, "ensemble is NULL");
+    if (dir != 0 && dir != 1) return fail(IGA_EINVAL, "dir must be 0 or 1");
+    if (lines != 1 && lines != 2 && lines != 4 && lines != 8 && lines != 16)
+        return fail(IGA_EINVAL, "lines must be 1, 2, 4, 8 or 16");
+    std::vector<Schedule> keep;
+    for (iga_plan *pl : ens->plans) keep.push_back(pl->sched[dir]);
+    iga_status st = set_window_all(ens, dir, lines, rows_per_lane);
+    if (st) {
+        for (size_t m = 0; m < ens->plans.size(); ++m) {
+            if (keep[m].win) (void)choose_window_schedule(ens->plans[m], dir, keep[m].lines, keep[m].mm);
+            else (void)choose_schedule(ens->plans[m], dir, keep[m].lines, keep[m].wpl);
+        }
         ens->unbind();
     }
     return st;
@@ -279,24 +318,33 @@ iga_status iga_ensemble_autotune(iga_ensemble *ens, void *const *T, void *const 
                 jobs[m] = {{R, R, OP_MY, -1, -1, pl->delta ? RF : nullptr, 0},
                            {RF, RF, OP_MY, -1, -1, pl->delta ? R : nullptr, 0}};
         }
-        int best_l = 0, best_w = 0;
+        int best_l = 0, best_w = 0, best_win = 0;
         float best_ms = 1e30f;
+        auto consider = [&](int lines, int w, int win) {
+            std::vector<BatchLaunch> bl;
+            if (build_sweep_batch(ens->plans, dir, jobs, bl) != IGA_OK) return;
+            float ms = time_launches(s, reps, [&] { return launch_all(bl, s); });
+            if (ms >= 0 && ms < best_ms) {
+                best_ms = ms;
+                best_l = lines;
+                best_w = w;
+                best_win = win;
+            }
+        };
+        for (int mm : {9, 13, 17, 25, 33})
+            for (int lines : {1, 2, 4, 8, 16})
+                if (set_window_all(ens, dir, lines, mm) == IGA_OK) consider(lines, mm, 1);
         for (int wpl : {1, 2, 4}) {
             for (int lines : {1, 2, 4, 8, 16}) {
                 if (lines * wpl > 16) continue;
                 if (set_schedule_all(ens, dir, lines, wpl) != IGA_OK) continue;
-                std::vector<BatchLaunch> bl;
-                if (build_sweep_batch(ens->plans, dir, jobs, bl) != IGA_OK) continue;
-                float ms = time_launches(s, reps, [&] { return launch_all(bl, s); });
-                if (ms >= 0 && ms < best_ms) {
-                    best_ms = ms;
-                    best_l = lines;
-                    best_w = wpl;
-                }
+                consider(lines, wpl, 0);
             }
         }
         if (!best_l) return fail(IGA_EUNSUPPORTED, "no line-solve schedule fits every member");
-        if ((st = set_schedule_all(ens, dir, best_l, best_w))) return st;
+        if ((st = best_win ? set_window_all(ens, dir, best_l, best_w)
+                           : set_schedule_all(ens, dir, best_l, best_w)))
+            return st;
     }
     IGA_HIP(hipStreamSynchronize(s));
     ens->unbind();

@@ -79,6 +79,24 @@ inline int op_dir(int op) { return (op == OP_AX || op == OP_MX) ? 0 : 1; }
 // consecutive rows (64*wpl chunks per line, lines padded to 64*wpl*mm rows).
 struct Schedule {
     int lines = 4, wpl = 1, mm = 17;
+    int win = 0;   // 1: windowed solves (see WinGeom), 0: exact chunk scan
+};
+
+// Windowed line solves (truncated partition): each lane restarts forward and
+// backward substitution from a zero state H rows outside its chunk.  Lanes
+// read their coefficient windows from strip tables at a per-lane base row:
+//   lane c < nhead               head strip, base off_head + c*mm
+//   tail0 <= c < tail1           tail strip, base off_tail + (c - tail0)*mm
+//   c >= tail1 (rows >= N only)  identity window at off_id
+//   otherwise                    canonical window at off_canon
+// Factor tables hold windows of H + mm + H rows (window row j is line row
+// c*mm - H + j); refinement rows (A, double) and explicit bands hold windows
+// of mm rows (the lane's own rows), with their own offsets (a*).
+struct WinGeom {
+    int H = 0;
+    int nhead = 0, tail0 = 0, tail1 = 0;
+    int off_head = 0, off_tail = 0, off_canon = 0, off_id = 0, nrows = 0;
+    int aoff_head = 0, aoff_tail = 0, aoff_canon = 0, aoff_id = 0, anrows = 0;
 };
 
 // Compressed coefficient tables of one banded operator (host copy).  Rows
@@ -91,11 +109,14 @@ struct Schedule {
 //   tb[c*P*P]           backward transfer matrix of chunk c
 struct OpHost {
     int K0 = 0, NK = 0, nrows = 0;
+    int H = 0;   // warm-up rows of windowed solves (0: decay too slow)
     std::vector<double> rows, a64, tf, tb;
+    std::vector<double> wrows, wa64;   // windowed strip tables (WinGeom)
 };
 struct BandHost {
     int K0 = 0, NK = 0, nrows = 0;
     std::vector<double> rows;   // band row r-P .. r+P
+    std::vector<double> wrows;  // windowed strip table (mm-row windows)
 };
 
 struct DirHost {
@@ -149,6 +170,9 @@ struct iga_plan {
     iga::BandHost band_host[iga::NBANDS];
     iga::DevBuf op_rows[iga::NOPS], op_a64c[iga::NOPS], op_tf[iga::NOPS], op_tb[iga::NOPS];
     iga::DevBuf band_rows[iga::NBANDS];
+    // windowed solve tables of the current schedules
+    iga::WinGeom wgeom[2];
+    iga::DevBuf op_wrows[iga::NOPS], op_wa64[iga::NOPS], band_wrows[iga::NBANDS];
     // assembly tables
     iga::DevBuf asm_bx, asm_by;                // [e][2][P+1][P+1]  (val, der), state precision
     iga::DevBuf asm_wx, asm_wy;                // wind remainders at x-qps / y-qps
@@ -166,6 +190,10 @@ iga_status upload_plan(iga_plan *pl);
 iga_status choose_schedule(iga_plan *pl, int dir, int lines, int wpl);
 iga_status build_solve_tables(iga_plan *pl);
 iga_status build_scan_tables(iga_plan *pl, int dir);
+int warmup_rows(const iga_plan *pl, int dir);   // 0 if a windowed solve is not accurate enough
+WinGeom window_geometry(const iga_plan *pl, int dir, int mm, int wpl);
+iga_status build_window_tables(iga_plan *pl, int dir);
+iga_status choose_window_schedule(iga_plan *pl, int dir, int lines, int mm);
 
 // kernels (factor.hip)
 iga_status launch_factor(iga_plan *pl, hipStream_t s);
@@ -183,6 +211,10 @@ struct SweepJob {
     int op1;          // solve applied to the band product (-1: none)
     const void *base; // added after the first solve (increment form), or NULL
     int add_after;    // 1: result = x + op1^{-1} band x; 0: result = op1^{-1} band x
+    // 1: a workgroup whose input lines are all zero leaves them untouched (set
+    // only for single solves whose result then equals dst's content: in place
+    // without base, or dst == base)
+    int zero_skip = 0;
 };
 iga_status launch_sweep(const iga_plan *pl, int dir, const SweepJob *jobs, int njobs,
                         hipStream_t s);
@@ -210,6 +242,9 @@ iga_status build_assemble_batch(const std::vector<iga_plan *> &pls, const std::v
 iga_status launch_batch(const BatchLaunch &b, hipStream_t s);
 iga_status sweep_prepare(const iga_plan *pl, int dir);
 size_t sweep_lds_bytes(const iga_plan *pl, int dir, int lines, int wpl);
+size_t wsweep_lds_bytes(const iga_plan *pl, int dir, int lines, int wpl, int mm);
+int wsweep_max_block(bool fp32, int mm);   // largest workgroup the windowed kernel allows
+iga_status wsweep_prepare(const iga_plan *pl, int dir);
 
 // kernels (util)
 iga_status launch_nonfinite(const iga_plan *pl, const void *T, const void *fuel, int *flag,

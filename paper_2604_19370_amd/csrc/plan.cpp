@@ -344,6 +344,204 @@ iga_status build_scan_tables(iga_plan *pl, int dir)
     return IGA_OK;
 }
 
+// ---------------------------------------------------------------------------
+// windowed solves: warm-up length and strip tables
+// ---------------------------------------------------------------------------
+// Forward substitution carries the state (y_r, .., y_{r-P+1}) through the
+// companion matrices C_r of the L rows; backward substitution carries
+// (x_r, .., x_{r+P-1}) through those of the scaled U rows.  Restarting either
+// from a zero state h rows early perturbs the result by the product of h
+// such matrices applied to the true state.  The warm-up is the smallest h
+// whose products from every start (head rows, the canonical interior, tail
+// rows) have infinity norm <= tol; 0 if none up to hmax.
+static int compute_warmup(const OpHost &o, int N, int P, double tol, int hmax)
+{
+    const int RS = 2 * P + 2;
+    auto row = [&](int r) { return &o.rows[(size_t)row_of(r, o.K0, o.NK, o.nrows) * RS]; };
+    auto worst = [&](bool fwd) {
+        std::vector<int> starts;
+        for (int s = 0; s < std::min(N, o.K0 + hmax + 2); ++s) starts.push_back(s);
+        for (int s = std::max(0, o.NK - hmax - 2); s < N; ++s) starts.push_back(s);
+        int h_need = 0;
+        for (int s : starts) {
+            std::vector<double> m((size_t)P * P, 0.0), n((size_t)P * P);
+            for (int i = 0; i < P; ++i) m[(size_t)i * P + i] = 1.0;
+            int h = 0;
+            for (;;) {
+                const int r = fwd ? s + h : s - h;
+                if (r < 0 || r >= N) break;   // reached the line end: exact from here
+                const double *c = row(r);
+                // n = C_r m
+                for (int j = 0; j < P; ++j) {
+                    double v = 0.0;
+                    for (int k = 0; k < P; ++k) v -= (fwd ? c[k] : c[P + 1 + k]) * m[(size_t)k * P + j];
+                    n[j] = v;
+                }
+                for (int i = 1; i < P; ++i)
+                    for (int j = 0; j < P; ++j) n[(size_t)i * P + j] = m[(size_t)(i - 1) * P + j];
+                m.swap(n);
+                ++h;
+                double nrm = 0.0;
+                for (int i = 0; i < P; ++i) {
+                    double rs = 0.0;
+                    for (int j = 0; j < P; ++j) rs += std::fabs(m[(size_t)i * P + j]);
+                    nrm = std::max(nrm, rs);
+                }
+                if (nrm <= tol) break;
+                if (h > hmax) return hmax + 1;
+            }
+            h_need = std::max(h_need, h);
+        }
+        return h_need;
+    };
+    const int h = std::max(worst(true), worst(false));
+    return h > hmax ? 0 : h;
+}
+
+int warmup_rows(const iga_plan *pl, int dir)
+{
+    int h = 0;
+    for (int op = 0; op < NOPS; ++op) {
+        if (op_dir(op) != dir) continue;
+        if (pl->op_host[op].H <= 0) return 0;
+        h = std::max(h, pl->op_host[op].H);
+    }
+    return (h + 3) & ~3;   // the kernels' warm-up loops step by 4 rows
+}
+
+// Geometry of the windowed tables of direction dir for rows-per-lane mm and
+// wpl wavefronts per line (H = 0 if windowed solves are not possible).
+WinGeom window_geometry(const iga_plan *pl, int dir, int mm, int wpl)
+{
+    const int N = dir ? pl->Ny : pl->Nx;
+    const int H = warmup_rows(pl, dir);
+    WinGeom g;
+    if (H <= 0) return g;
+    const int lanes = 64 * wpl;
+    g.H = H;
+    g.tail1 = std::min(lanes, (N + mm - 1) / mm);
+    // rows that are canonical in every table of the direction
+    int K0 = 0, NK = N;
+    for (int op = 0; op < NOPS; ++op)
+        if (op_dir(op) == dir) {
+            K0 = std::max(K0, pl->op_host[op].K0);
+            NK = std::min(NK, pl->op_host[op].NK);
+        }
+    for (int b = 0; b < NBANDS; ++b)
+        if ((b == BAND_BX ? 0 : 1) == dir) {
+            K0 = std::max(K0, pl->band_host[b].K0);
+            NK = std::min(NK, pl->band_host[b].NK);
+        }
+    // lane c is canonical iff rows [c mm - H, c mm + mm + H) lie in [K0, NK)
+    g.nhead = std::min(g.tail1, (K0 + H + mm - 1) / mm);
+    const int t0 = (NK - H - mm) >= 0 ? (NK - H - mm) / mm + 1 : 0;
+    g.tail0 = std::min(g.tail1, std::max(g.nhead, t0));
+    const int win = 2 * H + mm;
+    const int hrows = g.nhead > 0 ? g.nhead * mm + 2 * H : 0;
+    const int trows = g.tail1 > g.tail0 ? (g.tail1 - g.tail0) * mm + 2 * H : 0;
+    g.off_head = 0;
+    g.off_tail = hrows;
+    g.off_canon = hrows + trows;
+    g.off_id = g.off_canon + win;
+    g.nrows = g.off_id + win;
+    g.aoff_head = 0;
+    g.aoff_tail = g.nhead * mm;
+    g.aoff_canon = g.aoff_tail + (g.tail1 - g.tail0) * mm;
+    g.aoff_id = g.aoff_canon + mm;
+    g.anrows = g.aoff_id + mm;
+    return g;
+}
+
+// Strip tables of direction dir for the current windowed schedule.
+iga_status build_window_tables(iga_plan *pl, int dir)
+{
+    const Schedule &sc = pl->sched[dir];
+    const int N = dir ? pl->Ny : pl->Nx, P = pl->P, RS = 2 * P + 2, mm = sc.mm;
+    const WinGeom g = window_geometry(pl, dir, mm, sc.wpl);
+    if (g.H <= 0 || !sc.win) return fail(IGA_EUNSUPPORTED, "no windowed solve for this direction");
+    const int H = g.H;
+    pl->wgeom[dir] = g;
+    int K0 = 0, NK = N;
+    for (int op = 0; op < NOPS; ++op)
+        if (op_dir(op) == dir) {
+            K0 = std::max(K0, pl->op_host[op].K0);
+            NK = std::min(NK, pl->op_host[op].NK);
+        }
+    for (int b = 0; b < NBANDS; ++b)
+        if ((b == BAND_BX ? 0 : 1) == dir) {
+            K0 = std::max(K0, pl->band_host[b].K0);
+            NK = std::min(NK, pl->band_host[b].NK);
+        }
+    const int win = 2 * H + mm;
+    const int hrows = g.off_tail - g.off_head, trows = g.off_canon - g.off_tail;
+    const int ahrows = g.aoff_tail - g.aoff_head, atrows = g.aoff_canon - g.aoff_tail;
+    (void)NK;
+    // table content: line rows r (identity / zero rows outside [0, N)); the
+    // canonical window repeats line row rc (inside [K0, NK) when there is an
+    // interior; unused otherwise)
+    const int rc = std::min(K0, N - 1);
+    auto fill = [&](std::vector<double> &t, int nrows, int off, int r_first, int count,
+                    auto &&rowfn) {
+        (void)nrows;
+        for (int i = 0; i < count; ++i) rowfn(r_first + i, &t[(size_t)(off + i) * RS]);
+    };
+    iga_status st;
+    for (int op = 0; op < NOPS; ++op) {
+        if (op_dir(op) != dir) continue;
+        const OpHost &o = pl->op_host[op];
+        auto lu_row = [&](int r, double *dst) {
+            if (r < 0 || r >= N) {
+                std::fill(dst, dst + RS, 0.0);
+                dst[P] = 1.0;
+            } else {
+                const double *src = &o.rows[(size_t)row_of(r, o.K0, o.NK, o.nrows) * RS];
+                std::copy(src, src + RS, dst);
+            }
+        };
+        auto a_row = [&](int r, double *dst) {
+            if (r >= N) {
+                std::fill(dst, dst + RS, 0.0);
+                dst[P] = 1.0;
+            } else {
+                const double *src = &o.a64[(size_t)row_of(r, o.K0, o.NK, o.nrows) * RS];
+                std::copy(src, src + RS, dst);
+            }
+        };
+        OpHost &ow = pl->op_host[op];
+        ow.wrows.assign((size_t)g.nrows * RS, 0.0);
+        fill(ow.wrows, g.nrows, g.off_head, -H, hrows, lu_row);
+        fill(ow.wrows, g.nrows, g.off_tail, g.tail0 * mm - H, trows, lu_row);
+        for (int i = 0; i < win; ++i) lu_row(rc, &ow.wrows[(size_t)(g.off_canon + i) * RS]);
+        for (int i = 0; i < win; ++i) lu_row(-1, &ow.wrows[(size_t)(g.off_id + i) * RS]);
+        ow.wa64.assign((size_t)g.anrows * RS, 0.0);
+        fill(ow.wa64, g.anrows, g.aoff_head, 0, ahrows, a_row);
+        fill(ow.wa64, g.anrows, g.aoff_tail, g.tail0 * mm, atrows, a_row);
+        for (int i = 0; i < mm; ++i) a_row(rc, &ow.wa64[(size_t)(g.aoff_canon + i) * RS]);
+        for (int i = 0; i < mm; ++i) a_row(N, &ow.wa64[(size_t)(g.aoff_id + i) * RS]);
+        if ((st = upload_state(pl, pl->op_wrows[op], ow.wrows))) return st;
+        if (pl->fp32 && (st = upload_vec<double>(pl->op_wa64[op], ow.wa64))) return st;
+    }
+    for (int b = 0; b < NBANDS; ++b) {
+        if ((b == BAND_BX ? 0 : 1) != dir) continue;
+        BandHost &o = pl->band_host[b];
+        auto b_row = [&](int r, double *dst) {
+            if (r >= N) {
+                std::fill(dst, dst + RS, 0.0);
+            } else {
+                const double *src = &o.rows[(size_t)row_of(r, o.K0, o.NK, o.nrows) * RS];
+                std::copy(src, src + RS, dst);
+            }
+        };
+        o.wrows.assign((size_t)g.anrows * RS, 0.0);
+        fill(o.wrows, g.anrows, g.aoff_head, 0, ahrows, b_row);
+        fill(o.wrows, g.anrows, g.aoff_tail, g.tail0 * mm, atrows, b_row);
+        for (int i = 0; i < mm; ++i) b_row(rc, &o.wrows[(size_t)(g.aoff_canon + i) * RS]);
+        for (int i = 0; i < mm; ++i) b_row(N, &o.wrows[(size_t)(g.aoff_id + i) * RS]);
+        if ((st = upload_state(pl, pl->band_wrows[b], o.wrows))) return st;
+    }
+    return IGA_OK;
+}
+
 iga_status build_solve_tables(iga_plan *pl)
 {
     const int P = pl->P, RS = 2 * P + 2, W = 2 * P + 1;
@@ -381,6 +579,9 @@ iga_status build_solve_tables(iga_plan *pl)
         o.nrows = (int)(o.rows.size() / RS);
         if ((st = upload_state(pl, pl->op_rows[op], o.rows))) return st;
         if ((st = upload_vec<double>(pl->op_a64c[op], o.a64))) return st;
+        // windowed solves: below float resolution of the refined FP32 solve,
+        // below double rounding otherwise
+        o.H = compute_warmup(o, N, P, pl->fp32 ? std::ldexp(1.0, -30) : std::ldexp(1.0, -55), 96);
     }
     for (int dir = 0; dir < 2; ++dir)
         if ((st = build_scan_tables(pl, dir))) return st;
@@ -420,6 +621,7 @@ iga_status choose_schedule(iga_plan *pl, int dir, int lines, int wpl)
     const Schedule old = sc;
     sc.mm = mm;
     sc.wpl = wpl;
+    sc.win = 0;
     const int maxw = (!pl->fp32 && pl->P == 3 && mm >= 12) ? 8 : 16;   // wavefronts per workgroup
     if (lines <= 0) {
         // widest workgroup (<= 16 wavefronts) that fits LDS and still gives
@@ -444,9 +646,57 @@ iga_status choose_schedule(iga_plan *pl, int dir, int lines, int wpl)
     }
     sc.lines = lines;
     iga_status st;
-    if (old.wpl != sc.wpl || old.mm != sc.mm)
+    if (old.wpl != sc.wpl || old.mm != sc.mm || old.win)
         if ((st = build_scan_tables(pl, dir))) return st;
     return sweep_prepare(pl, dir);
+}
+
+// Windowed schedule of direction dir: `lines` lines per workgroup (0: the
+// widest that fits LDS and gives >= 256 workgroups), mm rows per lane in
+// {9, 13, 17, 25, 33} (0: 17); the wavefronts per line follow from the line
+// length.  IGA_EUNSUPPORTED if the operators decay too slowly for a
+// windowed solve or the schedule does not fit.
+iga_status choose_window_schedule(iga_plan *pl, int dir, int lines, int mm)
+{
+    const int N = dir ? pl->Ny : pl->Nx, nlines = dir ? pl->Nx : pl->Ny;
+    if (warmup_rows(pl, dir) <= 0)
+        return fail(IGA_EUNSUPPORTED, "the operators decay too slowly for windowed solves");
+    if (mm <= 0) mm = 17;
+    if (mm != 9 && mm != 13 && mm != 17 && mm != 25 && mm != 33)
+        return fail(IGA_EINVAL, "rows per lane must be 9, 13, 17, 25 or 33");
+    const int wpl = (N + 64 * mm - 1) / (64 * mm);
+    const int maxw = wsweep_max_block(pl->fp32, mm) / 64;
+    if (wpl > maxw)
+        return fail(IGA_EUNSUPPORTED, "lines of " + std::to_string(N) + " rows need more than " +
+                                          std::to_string(maxw) + " wavefronts at this rows-per-lane");
+    if (lines <= 0) {
+        lines = 0;
+        for (int w : {16, 8, 4, 2, 1}) {
+            if (w * wpl > maxw || wsweep_lds_bytes(pl, dir, w, wpl, mm) > 160 * 1024) continue;
+            if (!lines) lines = w;   // widest that fits
+            if ((nlines + w - 1) / w >= 256) { lines = w; break; }
+        }
+        if (!lines) return fail(IGA_EUNSUPPORTED, "windowed line buffers do not fit in LDS");
+    }
+    if (lines * wpl > maxw || (lines & (lines - 1)))
+        return fail(IGA_EUNSUPPORTED, "a workgroup holds at most " + std::to_string(maxw) +
+                                          " wavefronts (lines x waves per line) here");
+    if (wsweep_lds_bytes(pl, dir, lines, wpl, mm) > 160 * 1024)
+        return fail(IGA_EUNSUPPORTED, "windowed workgroup of " + std::to_string(lines) +
+                                          " lines does not fit in LDS");
+    Schedule &sc = pl->sched[dir];
+    const Schedule old = sc;
+    sc.lines = lines;
+    sc.wpl = wpl;
+    sc.mm = mm;
+    sc.win = 1;
+    iga_status st = build_window_tables(pl, dir);
+    if (!st) st = wsweep_prepare(pl, dir);
+    if (st) {
+        sc = old;
+        return st;
+    }
+    return IGA_OK;
 }
 
 }  // namespace iga

@@ -1,8 +1,11 @@
 // sweep_d3.hip -- line-solve kernels for double state, degree 3.
-#include "sweep_kernels.h"
+#include "sweep_win.h"
 
 namespace iga {
 SweepFn pick_sweep_d3(int mm, bool diry) { return pick_mm<double, 3>(mm, diry); }
 SweepBatchFn pick_sweep_batch_d3(int mm, bool diry) { return pick_mm_batch<double, 3>(mm, diry); }
+
+WSweepFn pick_wsweep_d3(int mm, bool diry) { return pick_wmm<double, 3>(mm, diry); }
+WSweepBatchFn pick_wsweep_batch_d3(int mm, bool diry) { return pick_wmm_batch<double, 3>(mm, diry); }
 
 }  // namespace iga

@@ -1,0 +1,474 @@
+// sweep_win.h -- windowed batched banded line solves (truncated partition).
+//
+// Section 4's directional solves are independent banded LU solves per line.
+// Here a workgroup owns W lines, each worked by WPL wavefronts; lane c of a
+// line holds rows [c*MM, c*MM + MM) in registers, and the line is kept in LDS
+// in two buffers with H zero rows before and after it.  Forward substitution
+// is a linear recurrence whose state contracts geometrically for these
+// mass-dominated operators (the L and U factors of a banded Toeplitz-like
+// matrix); restarting it from a zero state H rows before the chunk reproduces
+// the exact state to below the plan's tolerance, H computed by the plan from
+// the factors (products of the companion matrices).  So each lane:
+//   forward:  runs its H warm-up rows (input values read from LDS), then its
+//             own rows; publishes y to LDS;
+//   backward: runs H warm-up rows of y after its chunk, then its own rows.
+// No scan and no cross-lane arithmetic: lanes only meet in LDS, at barriers.
+// Rows outside [0, N) are identity rows with zero data, so the line ends are
+// exact.  FP32 plans refine once: x0 = LU32^{-1} b, r = b - A64 x0 in double,
+// x = x0 + LU32^{-1} r (as in the exact kernels).
+//
+// Coefficients come from strip tables in LDS (see WinGeom): each lane reads
+// window row j of its table at base + j*RS, base fixed per lane, so the
+// own-row loop uses compile-time offsets and no per-row index arithmetic.
+#pragma once
+#include "sweep_kernels.h"
+
+namespace iga {
+
+struct WinOpTab {
+    const void *rows;     // [nrows][RS] factor windows (state precision)
+    const double *a64;    // [anrows][RS] operator rows A(r, r-P .. r+P) (FP32 plans)
+};
+struct WinBandTab {
+    const void *rows;     // [anrows][RS] band rows r-P .. r+P (state precision)
+};
+
+struct WSweepParams {
+    SweepJob jobs[MAXJOBS];
+    WinOpTab ops[NOPS];
+    WinBandTab bands[NBANDS];
+    WinGeom g;
+    int N;        // line length
+    int nlines;   // lines
+    int ld;       // row stride of the field (Ny)
+    int Lb;       // LDS stride of one line buffer: H + 64*WPL*MM + H (+1 if even)
+    int W;        // lines per workgroup (power of two)
+    int WPL;      // wavefronts per line
+    int njobs;
+};
+
+template <typename T, int P, int MM> struct WinLane {
+    int r0;       // first row of the chunk
+    int wb;       // base row of the factor window (row r0 - H)
+    int ab;       // base row of the mm-row windows (row r0)
+};
+
+// forward substitution: warm-up rows from `in` (line buffer, row r at in[r]),
+// then the lane's own rows in x
+template <typename T, int P, int MM>
+__device__ __forceinline__ void wfwd(T (&x)[MM], const T *__restrict__ in, const T *__restrict__ tab,
+                                     const WinLane<T, P, MM> &ln, int H)
+{
+    constexpr int RS = RowStride<P>::RS;
+    T s[P];
+#pragma unroll
+    for (int j = 0; j < P; ++j) s[j] = T(0);
+    const T *d = in + ln.r0 - H;
+    const T *c = tab + (size_t)ln.wb * RS;
+    for (int j0 = 0; j0 < H; j0 += 4) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const T *L = c + (j0 + u) * RS;
+            T y = d[j0 + u];
+#pragma unroll
+            for (int j = P - 1; j >= 0; --j) y -= L[j] * s[j];
+#pragma unroll
+            for (int j = P - 1; j > 0; --j) s[j] = s[j - 1];
+            s[0] = y;
+        }
+    }
+    const T *co = c + (size_t)H * RS;
+#pragma unroll
+    for (int k = 0; k < MM; ++k) {
+        const T *L = co + k * RS;
+        T y = x[k];
+#pragma unroll
+        for (int j = P - 1; j >= 0; --j) y -= L[j] * s[j];
+#pragma unroll
+        for (int j = P - 1; j > 0; --j) s[j] = s[j - 1];
+        s[0] = y;
+        x[k] = y;
+    }
+}
+
+// backward substitution: warm-up rows of y after the chunk from `in`, then
+// the own rows
+template <typename T, int P, int MM>
+__device__ __forceinline__ void wbwd(T (&x)[MM], const T *__restrict__ in, const T *__restrict__ tab,
+                                     const WinLane<T, P, MM> &ln, int H)
+{
+    constexpr int RS = RowStride<P>::RS;
+    T t[P];
+#pragma unroll
+    for (int j = 0; j < P; ++j) t[j] = T(0);
+    const T *d = in + ln.r0 + MM;
+    const T *c = tab + ((size_t)ln.wb + H + MM) * RS + P;
+    for (int j0 = H - 4; j0 >= 0; j0 -= 4) {
+#pragma unroll
+        for (int u = 3; u >= 0; --u) {
+            const T *U = c + (j0 + u) * RS;
+            T v = d[j0 + u] * U[0];
+#pragma unroll
+            for (int j = P - 1; j >= 0; --j) v -= U[1 + j] * t[j];
+#pragma unroll
+            for (int j = P - 1; j > 0; --j) t[j] = t[j - 1];
+            t[0] = v;
+        }
+    }
+    const T *co = tab + ((size_t)ln.wb + H) * RS + P;
+#pragma unroll
+    for (int k = MM - 1; k >= 0; --k) {
+        const T *U = co + k * RS;
+        T v = x[k] * U[0];
+#pragma unroll
+        for (int j = P - 1; j >= 0; --j) v -= U[1 + j] * t[j];
+#pragma unroll
+        for (int j = P - 1; j > 0; --j) t[j] = t[j - 1];
+        t[0] = v;
+        x[k] = v;
+    }
+}
+
+template <typename T, int MM>
+__device__ __forceinline__ void publish(T *buf, const T (&x)[MM], int r0)
+{
+#pragma unroll
+    for (int k = 0; k < MM; ++k) buf[r0 + k] = x[k];
+}
+
+// One factored solve, x <- A^{-1} x.  `in` holds x's values for every lane
+// of the line (published, followed by a barrier); `tmp` is not being read.
+// On return `tmp` holds y and is still being read by other lanes.
+template <typename T, int P, int MM>
+__device__ __forceinline__ void wsolve(T (&x)[MM], const T *in, T *tmp, const T *tab,
+                                       const WinLane<T, P, MM> &ln, int H)
+{
+    wfwd<T, P, MM>(x, in, tab, ln, H);
+    publish<T, MM>(tmp, x, ln.r0);
+    __syncthreads();
+    wbwd<T, P, MM>(x, tmp, tab, ln, H);
+}
+
+// x <- A^{-1} x with one FP64-residual refinement for FP32 plans.  Entry:
+// `bin` holds x (published), `bout` not being read.  Exit: both buffers may
+// still be read by other lanes (the caller synchronises before reuse).
+template <typename T, int P, int MM>
+__device__ __forceinline__ void wsolve_refined(T (&x)[MM], T *bin, T *bout, const T *tab,
+                                               const double *a64, const WinLane<T, P, MM> &ln,
+                                               int H)
+{
+    if constexpr (sizeof(T) == 8) {
+        wsolve<T, P, MM>(x, bin, bout, tab, ln, H);
+    } else {
+        constexpr int RS = RowStride<P>::RS;
+        T b[MM];
+#pragma unroll
+        for (int k = 0; k < MM; ++k) b[k] = x[k];
+        wsolve<T, P, MM>(x, bin, bout, tab, ln, H);   // bin read (warm-up), bout = y
+        // x0 -> bin: bin's last readers passed the barrier inside wsolve
+        publish<T, MM>(bin, x, ln.r0);
+        __syncthreads();
+        // residual b - A64 x0 in double (neighbour rows from bin)
+        const double *a = a64 + (size_t)ln.ab * RS;
+        double xd[MM + 2 * P];
+#pragma unroll
+        for (int i = 0; i < P; ++i) {
+            xd[i] = (double)bin[ln.r0 - P + i];
+            xd[MM + P + i] = (double)bin[ln.r0 + MM + i];
+        }
+#pragma unroll
+        for (int k = 0; k < MM; ++k) xd[P + k] = (double)x[k];
+#pragma unroll
+        for (int k = 0; k < MM; ++k) {
+            double r = (double)b[k];
+#pragma unroll
+            for (int j = 0; j < 2 * P + 1; ++j) r -= a[k * RS + j] * xd[k + j];
+            b[k] = (T)r;
+        }
+        // r -> bout: bout's last readers (backward warm-up) passed the barrier above
+        publish<T, MM>(bout, b, ln.r0);
+        __syncthreads();
+        // correction: bin (x0) was last read by the residual, before that barrier
+        wsolve<T, P, MM>(b, bout, bin, tab, ln, H);
+#pragma unroll
+        for (int k = 0; k < MM; ++k) x[k] += b[k];
+    }
+}
+
+// One workgroup's work: W lines starting at line blk*W, job `jobi`.
+template <typename T, int P, int MM, bool DIRY>
+__device__ __forceinline__ void wsweep_body(const WSweepParams &prm, const int blk, const int jobi)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    constexpr int RS = RowStride<P>::RS;
+    constexpr bool F32 = sizeof(T) == 4;
+    const SweepJob job = prm.jobs[jobi];
+    const WinGeom &g = prm.g;
+    const int H = g.H;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int W = prm.W, WPL = prm.WPL;
+    const int wlog = __builtin_ctz(W);
+    const int rstep = blockDim.x >> wlog;
+    const int N = prm.N, Lb = prm.Lb, ld = prm.ld;
+    const int line0 = blk * W;
+    const int nl = min(W, prm.nlines - line0);
+    const int lw = wave / WPL;
+    const int part = wave - lw * WPL;
+
+    // LDS: two line buffers [W][Lb] (row r of line l at H + l*Lb + r), then
+    // the tables of this job
+    T *bufA = reinterpret_cast<T *>(smem);
+    T *bufB = bufA + (size_t)W * Lb;
+    size_t off = ((size_t)2 * W * Lb * sizeof(T) + 15) & ~(size_t)15;
+    auto take = [&](size_t bytes) {
+        unsigned char *p = smem + off;
+        off += (bytes + 15) & ~(size_t)15;
+        return p;
+    };
+    const T *tab0 = nullptr, *tab1 = nullptr, *btab = nullptr;
+    const double *a640 = nullptr, *a641 = nullptr;
+    auto stage_op = [&](const WinOpTab &t, const T *&rows, const double *&a) {
+        T *r = reinterpret_cast<T *>(take((size_t)g.nrows * RS * sizeof(T)));
+        stage_table<T>(r, t.rows, g.nrows * RS);
+        rows = r;
+        if (F32) {
+            double *d = reinterpret_cast<double *>(take((size_t)g.anrows * RS * sizeof(double)));
+            stage_table<double>(d, t.a64, g.anrows * RS);
+            a = d;
+        }
+    };
+    const bool has0 = job.op0 >= 0, has1 = job.op1 >= 0, hasb = job.band >= 0;
+    int *flag = reinterpret_cast<int *>(take(16));   // workgroup-wide "input not all zero"
+    if (tid == 0) *flag = 0;
+    if (has0) stage_op(prm.ops[job.op0], tab0, a640);
+    if (has1) stage_op(prm.ops[job.op1], tab1, a641);
+    if (hasb) {
+        T *r = reinterpret_cast<T *>(take((size_t)g.anrows * RS * sizeof(T)));
+        stage_table<T>(r, prm.bands[job.band].rows, g.anrows * RS);
+        btab = r;
+    }
+    // zero the pads of every line buffer: [0, H) and [H + N, Lb)
+    for (int i = tid; i < 2 * W * H; i += blockDim.x) {
+        const int l = i / H, r = i - l * H;
+        bufA[(size_t)l * Lb + r] = T(0);
+    }
+    const int tailn = Lb - H - N;
+    for (int i = tid; i < 2 * W * tailn; i += blockDim.x) {
+        const int l = i / tailn, r = i - l * tailn;
+        bufA[(size_t)l * Lb + H + N + r] = T(0);
+    }
+
+    // Stage W lines of a field into buffer `buf` (row r of line l at
+    // buf[l*Lb + H + r]) and back.  The full rows are copied in unconditional
+    // batches of 8 per thread (loads issued before their stores); only the
+    // last partial row is guarded.  y-lines: each line is a contiguous run of
+    // N values.  x-lines: rows of W consecutive columns; a workgroup slot past
+    // the last line copies a live column into its own (unused) buffer.
+    const int bd = blockDim.x;
+    auto copy_run_in = [&](const T *src, T *dst, int n) {
+        const int nfull = (n / bd) * bd;
+        int b0 = 0;
+        for (; b0 + 8 * bd <= nfull; b0 += 8 * bd) {
+            T v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) v[u] = src[b0 + u * bd + tid];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) dst[b0 + u * bd + tid] = v[u];
+        }
+        for (; b0 < nfull; b0 += bd) dst[b0 + tid] = src[b0 + tid];
+        if (b0 + tid < n) dst[b0 + tid] = src[b0 + tid];
+    };
+    const int jcol = tid & (W - 1), r00 = tid >> wlog;
+    auto load_lines = [&](const T *src, T *buf) {
+        if constexpr (DIRY) {
+            for (int l = 0; l < nl; ++l)
+                copy_run_in(src + (size_t)(line0 + l) * ld, buf + (size_t)l * Lb + H, N);
+        } else {
+            const T *s = src + line0 + min(jcol, nl - 1);
+            T *d = buf + (size_t)jcol * Lb + H;
+            const int nfull = (N / rstep) * rstep;
+            int b0 = 0;
+            for (; b0 + 8 * rstep <= nfull; b0 += 8 * rstep) {
+                T v[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) v[u] = s[(size_t)(b0 + u * rstep + r00) * ld];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) d[b0 + u * rstep + r00] = v[u];
+            }
+            for (; b0 < nfull; b0 += rstep) d[b0 + r00] = s[(size_t)(b0 + r00) * ld];
+            if (b0 + r00 < N) d[b0 + r00] = s[(size_t)(b0 + r00) * ld];
+        }
+    };
+    auto store_lines = [&](T *dst, const T *buf) {
+        if constexpr (DIRY) {
+            for (int l = 0; l < nl; ++l)
+                copy_run_in(buf + (size_t)l * Lb + H, dst + (size_t)(line0 + l) * ld, N);
+        } else {
+            if (jcol < nl) {
+                T *d = dst + line0 + jcol;
+                const T *b = buf + (size_t)jcol * Lb + H;
+                const int nfull = (N / rstep) * rstep;
+                int b0 = 0;
+                for (; b0 + 8 * rstep <= nfull; b0 += 8 * rstep) {
+                    T v[8];
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) v[u] = b[b0 + u * rstep + r00];
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) d[(size_t)(b0 + u * rstep + r00) * ld] = v[u];
+                }
+                for (; b0 < nfull; b0 += rstep) d[(size_t)(b0 + r00) * ld] = b[b0 + r00];
+                if (b0 + r00 < N) d[(size_t)(b0 + r00) * ld] = b[b0 + r00];
+            }
+        }
+    };
+
+    // this lane's chunk and table windows
+    const int c = part * 64 + lane;
+    WinLane<T, P, MM> ln;
+    ln.r0 = c * MM;
+    if (c < g.nhead) {
+        ln.wb = g.off_head + c * MM;
+        ln.ab = g.aoff_head + c * MM;
+    } else if (c >= g.tail1) {
+        ln.wb = g.off_id;
+        ln.ab = g.aoff_id;
+    } else if (c >= g.tail0) {
+        ln.wb = g.off_tail + (c - g.tail0) * MM;
+        ln.ab = g.aoff_tail + (c - g.tail0) * MM;
+    } else {
+        ln.wb = g.off_canon;
+        ln.ab = g.aoff_canon;
+    }
+    // slots beyond nl (the last workgroup) compute on their own, unused buffers
+    T *A = bufA + (size_t)lw * Lb + H;
+    T *B = bufB + (size_t)lw * Lb + H;
+    const bool live = lw < nl;
+
+    load_lines(static_cast<const T *>(job.src), bufA);
+    __syncthreads();
+    T x[MM];
+#pragma unroll
+    for (int k = 0; k < MM; ++k) x[k] = live ? A[ln.r0 + k] : T(0);
+    if (job.zero_skip) {
+        // all-zero input lines: the result (zero, or the base it is added to)
+        // is already in dst
+        bool nz = false;
+#pragma unroll
+        for (int k = 0; k < MM; ++k) nz = nz || x[k] != T(0);
+        if (__any(nz) && lane == 0) *flag = 1;
+        __syncthreads();
+        if (!*flag) return;   // the same value for every thread of the workgroup
+    }
+    // A: input published; B: free
+    if (has0) {
+        wsolve_refined<T, P, MM>(x, A, B, tab0, a640, ln, H);
+        __syncthreads();
+    }
+    if (job.base) {
+        // increment form: the solve produced x - base; add the base state
+        load_lines(static_cast<const T *>(job.base), bufB);
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < MM; ++k) x[k] += live ? B[ln.r0 + k] : T(0);
+        __syncthreads();
+    }
+    if (hasb) {
+        // explicit Crank-Nicolson operator along the line, then the second solve
+        publish<T, MM>(A, x, ln.r0);
+        __syncthreads();
+        T xd[MM + 2 * P];
+#pragma unroll
+        for (int i = 0; i < P; ++i) {
+            xd[i] = A[ln.r0 - P + i];
+            xd[MM + P + i] = A[ln.r0 + MM + i];
+        }
+#pragma unroll
+        for (int k = 0; k < MM; ++k) xd[P + k] = x[k];
+        T y[MM];
+        const T *bt = btab + (size_t)ln.ab * RS;
+#pragma unroll
+        for (int k = 0; k < MM; ++k) {
+            T v = T(0);
+#pragma unroll
+            for (int j = 0; j < 2 * P + 1; ++j) v += bt[k * RS + j] * xd[k + j];
+            y[k] = v;
+        }
+        // y -> B (free since the last barrier), then solve with A as scratch
+        publish<T, MM>(B, y, ln.r0);
+        __syncthreads();
+        if (has1) {
+            wsolve_refined<T, P, MM>(y, B, A, tab1, a641, ln, H);
+            __syncthreads();
+        }
+        if (job.add_after) {
+#pragma unroll
+            for (int k = 0; k < MM; ++k) x[k] += y[k];
+        } else {
+#pragma unroll
+            for (int k = 0; k < MM; ++k) x[k] = y[k];
+        }
+    }
+    if (live) publish<T, MM>(A, x, ln.r0);
+    __syncthreads();
+    store_lines(static_cast<T *>(job.dst), bufA);
+}
+
+// workgroup size bound: 16 wavefronts, or 8 for large windows, which need
+// more than 128 registers per lane
+template <typename T, int P, int MM> constexpr int wsweep_max_threads()
+{
+    return (MM >= 25 || (sizeof(T) == 8 && MM >= 17)) ? 512 : 1024;
+}
+
+template <typename T, int P, int MM, bool DIRY>
+__global__ __launch_bounds__((wsweep_max_threads<T, P, MM>())) void k_wsweep(WSweepParams prm)
+{
+    wsweep_body<T, P, MM, DIRY>(prm, xcd_remap(blockIdx.x, gridDim.x), blockIdx.y);
+}
+
+template <typename T, int P, int MM, bool DIRY>
+__global__ __launch_bounds__((wsweep_max_threads<T, P, MM>())) void k_wsweep_batch(
+    const WSweepParams *__restrict__ prms, const int2 *__restrict__ info)
+{
+    const int2 bi = info[xcd_remap(blockIdx.x, gridDim.x)];
+    if (bi.x < 0) return;
+    const WSweepParams &prm = prms[bi.x];
+    if ((int)blockIdx.y >= prm.njobs) return;
+    wsweep_body<T, P, MM, DIRY>(prm, bi.y, blockIdx.y);
+}
+
+using WSweepFn = void (*)(WSweepParams);
+using WSweepBatchFn = void (*)(const WSweepParams *, const int2 *);
+
+#define IGA_WSWEEP_MMS(X) X(9) X(13) X(17) X(25) X(33)
+
+template <typename T, int P> static WSweepFn pick_wmm(int mm, bool diry)
+{
+#define IGA_CASE(MM_) \
+    if (mm == MM_) return diry ? k_wsweep<T, P, MM_, true> : k_wsweep<T, P, MM_, false>;
+    IGA_WSWEEP_MMS(IGA_CASE)
+#undef IGA_CASE
+    return nullptr;
+}
+
+template <typename T, int P> static WSweepBatchFn pick_wmm_batch(int mm, bool diry)
+{
+#define IGA_CASE(MM_) \
+    if (mm == MM_) return diry ? k_wsweep_batch<T, P, MM_, true> : k_wsweep_batch<T, P, MM_, false>;
+    IGA_WSWEEP_MMS(IGA_CASE)
+#undef IGA_CASE
+    return nullptr;
+}
+
+WSweepFn pick_wsweep_f2(int mm, bool diry);
+WSweepFn pick_wsweep_f3(int mm, bool diry);
+WSweepFn pick_wsweep_d2(int mm, bool diry);
+WSweepFn pick_wsweep_d3(int mm, bool diry);
+WSweepBatchFn pick_wsweep_batch_f2(int mm, bool diry);
+WSweepBatchFn pick_wsweep_batch_f3(int mm, bool diry);
+WSweepBatchFn pick_wsweep_batch_d2(int mm, bool diry);
+WSweepBatchFn pick_wsweep_batch_d3(int mm, bool diry);
+
+}  // namespace iga

@@ -23,9 +23,11 @@ WIND_CONST, WIND_SINCOS = 0, 1
 EXPORTED = ("iga_default_coeffs", "iga_plan_create", "iga_plan_destroy", "iga_plan_dims",
             "iga_factor_1d", "iga_assemble_rhs", "iga_line_solve", "iga_step", "iga_run",
             "iga_plan_schedule", "iga_plan_set_schedule", "iga_plan_set_assembly_rows",
-            "iga_plan_assembly_rows", "iga_autotune", "iga_ensemble_create", "iga_ensemble_destroy",
+            "iga_plan_assembly_rows", "iga_autotune", "iga_plan_set_window_schedule",
+            "iga_plan_solver", "iga_ensemble_create", "iga_ensemble_destroy",
             "iga_ensemble_size", "iga_ensemble_launches", "iga_ensemble_step", "iga_ensemble_run",
-            "iga_ensemble_set_schedule", "iga_ensemble_set_assembly_rows", "iga_ensemble_autotune",
+            "iga_ensemble_set_schedule", "iga_ensemble_set_window_schedule",
+            "iga_ensemble_set_assembly_rows", "iga_ensemble_autotune",
             "iga_last_error")
 
 _COEFF_NAMES = ("c_adv", "c_diff", "c_react", "c_nld", "c_ign", "t_ig", "fuel_thr", "t_act",
@@ -84,6 +86,9 @@ def lib() -> ctypes.CDLL:
         L.iga_plan_assembly_rows.argtypes = [vp]
         L.iga_plan_assembly_rows.restype = i32
         L.iga_autotune.argtypes = [vp, vp, vp, i32, vp]
+        L.iga_plan_set_window_schedule.argtypes = [vp, i32, i32, i32]
+        L.iga_plan_solver.argtypes = [vp, i32, ctypes.POINTER(i32), ctypes.POINTER(i32)]
+        L.iga_ensemble_set_window_schedule.argtypes = [vp, i32, i32, i32]
         pp = ctypes.POINTER(vp)
         L.iga_ensemble_create.argtypes = [ctypes.POINTER(PlanDesc), i32, ctypes.POINTER(vp)]
         L.iga_ensemble_destroy.argtypes = [vp]
@@ -245,6 +250,16 @@ class Plan:
     def set_assembly_rows(self, rows):
         _check(lib().iga_plan_set_assembly_rows(self._h, int(rows)), "iga_plan_set_assembly_rows")
 
+    def set_window_schedule(self, dir, lines, rows_per_lane=0):
+        _check(lib().iga_plan_set_window_schedule(self._h, int(dir), int(lines), int(rows_per_lane)),
+               "iga_plan_set_window_schedule")
+
+    def solver(self, dir):
+        w, h = ctypes.c_int32(), ctypes.c_int32()
+        _check(lib().iga_plan_solver(self._h, int(dir), ctypes.byref(w), ctypes.byref(h)),
+               "iga_plan_solver")
+        return dict(windowed=bool(w.value), warmup=h.value)
+
 
 class Ensemble:
     """An iga_ensemble: member plans stepped together by batched launches.
@@ -315,6 +330,11 @@ class Ensemble:
     def set_schedule(self, dir, lines, waves_per_line=1):
         _check(lib().iga_ensemble_set_schedule(self._h, int(dir), int(lines), int(waves_per_line)),
                "iga_ensemble_set_schedule")
+
+    def set_window_schedule(self, dir, lines, rows_per_lane=17):
+        _check(lib().iga_ensemble_set_window_schedule(self._h, int(dir), int(lines),
+                                                      int(rows_per_lane)),
+               "iga_ensemble_set_window_schedule")
 
     def set_assembly_rows(self, rows):
         _check(lib().iga_ensemble_set_assembly_rows(self._h, int(rows)),

@@ -86,6 +86,50 @@ def test_line_solve_every_schedule(dir, lines, wpl, n, p):
             assert rel(host(x), oracle.line_solve(od, dir, which, X)) < tol
 
 
+@pytest.mark.parametrize("dir", [0, 1])
+@pytest.mark.parametrize("lines", [1, 2, 4, 16])
+@pytest.mark.parametrize("mm", [9, 13, 17, 25, 33])
+@pytest.mark.parametrize("n", [150, 600])
+@pytest.mark.parametrize("p", [2, 3])
+def test_line_solve_every_window_schedule(dir, lines, mm, n, p):
+    """Windowed solves (zero-state restarts `warmup` rows outside each chunk)
+    against the oracle's banded LU, for every compiled rows-per-lane."""
+    print(f"window schedule dir{dir} lines{lines} mm{mm} n{n} p{p}", flush=True)
+    sc = inputs.small_case(8, n, n - 17, p, "strang")
+    for precision, tol in (("fp64", TOL64), ("fp32", TOL32)):
+        pl, od = plan_and_oracle(sc, precision)
+        if p == 2:
+            assert pl.solver(dir)["warmup"] > 0
+        try:
+            pl.set_window_schedule(dir, lines, mm)
+        except iga.IgaError as e:
+            assert e.status == iga.EUNSUPPORTED
+            continue
+        assert pl.solver(dir)["windowed"]
+        X = np.random.default_rng(lines + mm).standard_normal((n + p, n - 17 + p))
+        for which in (0, 1, 2) if dir == 1 else (0, 1):
+            x = dev(X, precision == "fp32")
+            pl.line_solve(dir, which, x)
+            assert rel(host(x), oracle.line_solve(od, dir, which, X)) < tol
+
+
+def test_stiff_operators_fall_back_to_exact_solves():
+    """With a time step far above the diffusive scale the implicit operators
+    lose their fast decay (interior root of the forward recurrence ~0.945 at
+    dt = 400, h = 1: ~680 rows to reach 2^-55); on lines longer than that the
+    plan keeps the exact chunk-scan solves, and steps still match the oracle.
+    (On short lines a warm-up that reaches the line end is exact, so windowed
+    solves stay available there.)"""
+    sc = inputs.small_case(9, 200, 36, 2, "pr", dt=400.0)
+    pl, od = plan_and_oracle(sc, "fp64", coeffs=dict(c_nld=0.0, c_ign=0.0, c_rad=0.0,
+                                                      c_forcing=0.0))
+    assert pl.solver(0) == {"windowed": False, "warmup": 0}
+    T, F = dev(sc.T0), dev(sc.fuel0)
+    pl.step(T, F)
+    To, Fo = oracle.step(od, sc.T0, sc.fuel0)
+    assert rel(host(T), To) < TOL64 and rel(host(F), Fo) < TOL64
+
+
 def test_line_solve_fp32_refined_accuracy():
     """FP32 solve + one FP64-residual refinement: error near float rounding of the
     result, well below an unrefined FP32 solve's cond * eps."""
