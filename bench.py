@@ -42,7 +42,11 @@ def parse():
                     help="only launch each kernel of the FP32 step --kernel-reps times, plus a "
                          "copy kernel of known size (for profiler runs)")
     ap.add_argument("--schedule", type=str, default=None,
-                    help="fixed schedule 'xlines,xwpl,ylines,ywpl,asmrows' instead of autotuning")
+                    help="fixed exact line-solve schedule 'xlines,xwpl,ylines,ywpl,asmrows' "
+                         "instead of autotuning")
+    ap.add_argument("--window-schedule", type=str, default=None,
+                    help="fixed windowed line-solve schedule 'xlines,xrows,ylines,yrows,asmrows' "
+                         "(rows per lane) instead of autotuning")
     ap.add_argument("--no-ensembles", action="store_true",
                     help="skip the ensemble workloads (64 uneven members; 16 cubic 2048^2 members)")
     return ap.parse_args()
@@ -192,10 +196,14 @@ def copy_kernel(n_bytes, reps, torch):
     torch.cuda.synchronize()
 
 
-def apply_schedule(pl, spec):
+def apply_schedule(pl, spec, windowed=False):
     xl, xw, yl, yw, ar = (int(v) for v in spec.split(","))
-    pl.set_schedule(0, xl, xw)
-    pl.set_schedule(1, yl, yw)
+    if windowed:
+        pl.set_window_schedule(0, xl, xw)
+        pl.set_window_schedule(1, yl, yw)
+    else:
+        pl.set_schedule(0, xl, xw)
+        pl.set_schedule(1, yl, yw)
     pl.set_assembly_rows(ar)
 
 
@@ -286,6 +294,8 @@ def main():
         pl.factor()
         if args.schedule:
             apply_schedule(pl, args.schedule)
+        if args.window_schedule:
+            apply_schedule(pl, args.window_schedule, windowed=True)
         kt = kernel_times(pl, sc, args.kernel_reps, torch)
         copy_kernel(4 * sc.ndof, args.kernel_reps, torch)
         print(json.dumps({"kernel_us": {k: round(v * 1e6, 2) for k, v in kt.items()},
@@ -303,6 +313,8 @@ def main():
         Ft = torch.tensor(sc.fuel0, dtype=pl.dtype, device="cuda")
         if args.schedule:
             apply_schedule(pl, args.schedule)
+        elif args.window_schedule and prec == "fp32":
+            apply_schedule(pl, args.window_schedule, windowed=True)
         else:
             pl.autotune(Tt, Ft, reps=10)      # untimed: picks tiles / workgroup widths
         del Tt, Ft
