@@ -132,10 +132,11 @@ def assembly_flops(p, fuel):
 
 KERNEL_FAMILY = {"assemble_s1_fuel": "k_assemble<float,p=2,fuel=true>",
                  "assemble_s3": "k_assemble<float,p=2,fuel=false>",
-                 "sweep_x_A": "k_sweep<float,p=2,m=17,x-lines>",
-                 "sweep_y_M": "k_sweep<float,p=2,m=17,y-lines>",
-                 "sweep_y_cn": "k_sweep<float,p=2,m=17,y-lines>"}
-SOURCES = {"k_assemble": ("assemble.hip",), "k_sweep": ("sweep_kernels.h", "sweep.hip")}
+                 "sweep_x_A": "k_wsweep<float,p=2,x-lines>",
+                 "sweep_y_M": "k_wsweep<float,p=2,y-lines>",
+                 "sweep_y_cn": "k_wsweep<float,p=2,y-lines>"}
+SOURCES = {"k_assemble": ("assemble.hip",),
+           "k_wsweep": ("sweep_win.h", "sweep_kernels.h", "sweep.hip")}
 
 
 def measured_traffic(kernel, nel):
@@ -299,7 +300,8 @@ def main():
         kt = kernel_times(pl, sc, args.kernel_reps, torch)
         copy_kernel(4 * sc.ndof, args.kernel_reps, torch)
         print(json.dumps({"kernel_us": {k: round(v * 1e6, 2) for k, v in kt.items()},
-                          "schedules": [pl.schedule(0), pl.schedule(1),
+                          "schedules": [dict(pl.schedule(0), **pl.solver(0)),
+                                        dict(pl.schedule(1), **pl.solver(1)),
                                         {"assembly_rows": pl.assembly_rows}],
                           "copy_bytes": 4 * sc.ndof}), flush=True)
         pl.close()
@@ -320,7 +322,9 @@ def main():
         del Tt, Ft
         wall, ev, T, F = time_steps(pl, sc, args.steps, args.warmup, torch)
         res[prec] = dict(wall=wall, ev=ev, dofs=sc.ndof * args.steps / wall,
-                         sched=[pl.schedule(0), pl.schedule(1), {"assembly_rows": pl.assembly_rows}])
+                         sched=[dict(pl.schedule(0), **pl.solver(0)),
+                                dict(pl.schedule(1), **pl.solver(1)),
+                                {"assembly_rows": pl.assembly_rows}])
         ktimes[prec] = kernel_times(pl, sc, args.kernel_reps, torch)
         pl.close()
 
