@@ -27,7 +27,8 @@ FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
          f"-I{os.path.join(ROOT, 'include')}"]
 
 SOURCES = ["plan.cpp", "api.cpp", "ensemble.cpp", "factor.hip", "assemble.hip", "sweep.hip",
-           "sweep_f2.hip", "sweep_f3.hip", "sweep_d2.hip", "sweep_d3.hip"]
+           "sweep_f1.hip", "sweep_f2.hip", "sweep_f3.hip", "sweep_d1.hip", "sweep_d2.hip",
+           "sweep_d3.hip"]
 
 
 def _compile(src: str) -> tuple[str, float, str]:

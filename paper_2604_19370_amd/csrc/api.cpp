@@ -39,7 +39,7 @@ static bool aligned(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 15
 iga_status check_desc(const iga_plan_desc *d)
 {
     if (!d) return fail(IGA_EINVAL, "desc is NULL");
-    if (d->p != 2 && d->p != 3) return fail(IGA_EINVAL, "p must be 2 or 3");
+    if (d->p < 1 || d->p > 3) return fail(IGA_EINVAL, "p must be 1, 2 or 3");
     if (d->nel_x < 2 * d->p + 1 || d->nel_y < 2 * d->p + 1)
         return fail(IGA_EINVAL, "nel_x and nel_y must be >= 2p+1");
     if (d->nel_x > 65536 || d->nel_y > 65536) return fail(IGA_EINVAL, "nel above 65536");

@@ -114,13 +114,13 @@ __device__ __forceinline__ void assemble_body(const AsmParams<T> &a, const int g
         fb[0] = f0;
         cb[1] = lane_ahead<1>(c0, c1, lane);
         fb[1] = lane_ahead<1>(f0, f1, lane);
-        if (Q > 2) {
+        if constexpr (Q > 2) {
             cb[2] = lane_ahead<2>(c0, c1, lane);
             fb[2] = lane_ahead<2>(f0, f1, lane);
         }
-        if (Q > 3) {
-            cb[Q - 1] = lane_ahead<(Q > 3 ? 3 : 1)>(c0, c1, lane);
-            fb[Q - 1] = lane_ahead<(Q > 3 ? 3 : 1)>(f0, f1, lane);
+        if constexpr (Q > 3) {
+            cb[3] = lane_ahead<3>(c0, c1, lane);
+            fb[3] = lane_ahead<3>(f0, f1, lane);
         }
         mx = cb[0];
 #pragma unroll
@@ -277,13 +277,13 @@ __device__ __forceinline__ void assemble_body(const AsmParams<T> &a, const int g
             }
             T r = pb[0] + lane_behind<1>(pb[1]);
             T rf = FUEL ? pf[0] + lane_behind<1>(pf[1]) : T(0);
-            if (Q > 2) {
+            if constexpr (Q > 2) {
                 r += lane_behind<2>(pb[2]);
                 if (FUEL) rf += lane_behind<2>(pf[2]);
             }
-            if (Q > 3) {
-                r += lane_behind<(Q > 3 ? 3 : 1)>(pb[Q - 1]);
-                if (FUEL) rf += lane_behind<(Q > 3 ? 3 : 1)>(pf[Q - 1]);
+            if constexpr (Q > 3) {
+                r += lane_behind<3>(pb[3]);
+                if (FUEL) rf += lane_behind<3>(pf[3]);
             }
             if (lane >= P && colA < Ny) {
                 a.R[(size_t)ex * Ny + colA] = r;
@@ -300,12 +300,17 @@ __device__ __forceinline__ void assemble_body(const AsmParams<T> &a, const int g
     for (; k + Q <= K; k += Q) {
         step(Ic<0>{}, k);
         step(Ic<1>{}, k + 1);
-        step(Ic<2>{}, k + 2);
-        if (Q > 3) step(Ic<(Q > 3 ? 3 : 0)>{}, k + 3);
+        if constexpr (Q > 2) step(Ic<2>{}, k + 2);
+        if constexpr (Q > 3) step(Ic<3>{}, k + 3);
     }
+    // fewer than Q steps remain
     if (k < K) step(Ic<0>{}, k);
-    if (k + 1 < K) step(Ic<1>{}, k + 1);
-    if (Q > 3 && k + 2 < K) step(Ic<2>{}, k + 2);
+    if constexpr (Q > 2) {
+        if (k + 1 < K) step(Ic<1>{}, k + 1);
+    }
+    if constexpr (Q > 3) {
+        if (k + 2 < K) step(Ic<2>{}, k + 2);
+    }
 }
 
 template <typename T, int P, bool FUEL>
@@ -417,7 +422,10 @@ static iga_status launch_t(const iga_plan *pl, int substep, const void *S, const
     const bool fuel = RF != nullptr;
 #define IGA_ASM(P_, FU_) \
     hipLaunchKernelGGL((k_assemble<T, P_, FU_>), dim3(blocks), dim3(256), 0, s, a)
-    if (P == 2) {
+    if (P == 1) {
+        if (fuel) IGA_ASM(1, true);
+        else IGA_ASM(1, false);
+    } else if (P == 2) {
         if (fuel) IGA_ASM(2, true);
         else IGA_ASM(2, false);
     } else if (P == 3) {
@@ -457,7 +465,10 @@ static iga_status batch_t(const std::vector<iga_plan *> &pls, const std::vector<
     while (info.size() % 4) info.push_back(int2{-1, 0});
     const void *fn = nullptr;
 #define IGA_ASMB(P_, FU_) fn = reinterpret_cast<const void *>(k_assemble_batch<T, P_, FU_>)
-    if (P == 2) {
+    if (P == 1) {
+        if (fuel) IGA_ASMB(1, true);
+        else IGA_ASMB(1, false);
+    } else if (P == 2) {
         if (fuel) IGA_ASMB(2, true);
         else IGA_ASMB(2, false);
     } else if (P == 3) {

@@ -83,7 +83,9 @@ iga_status launch_factor(iga_plan *pl, hipStream_t s)
     auto d_lf = reinterpret_cast<double *const *>(mp + sizeof(bands));
     auto d_uf = reinterpret_cast<double *const *>(mp + sizeof(bands) + sizeof(lf));
     auto d_N = reinterpret_cast<const int *>(mp + sizeof(bands) + sizeof(lf) + sizeof(uf));
-    if (pl->P == 2)
+    if (pl->P == 1)
+        hipLaunchKernelGGL(k_band_lu<1>, dim3(1), dim3(64), 0, s, d_bands, d_lf, d_uf, d_N, (int)NOPS);
+    else if (pl->P == 2)
         hipLaunchKernelGGL(k_band_lu<2>, dim3(1), dim3(64), 0, s, d_bands, d_lf, d_uf, d_N, (int)NOPS);
     else if (pl->P == 3)
         hipLaunchKernelGGL(k_band_lu<3>, dim3(1), dim3(64), 0, s, d_bands, d_lf, d_uf, d_N, (int)NOPS);

@@ -6,9 +6,11 @@ namespace iga {
 static SweepFn pick_fn(bool fp32, int P, int mm, bool diry)
 {
     if (fp32) {
+        if (P == 1) return pick_sweep_f1(mm, diry);
         if (P == 2) return pick_sweep_f2(mm, diry);
         if (P == 3) return pick_sweep_f3(mm, diry);
     } else {
+        if (P == 1) return pick_sweep_d1(mm, diry);
         if (P == 2) return pick_sweep_d2(mm, diry);
         if (P == 3) return pick_sweep_d3(mm, diry);
     }
@@ -63,9 +65,11 @@ iga_status sweep_prepare(const iga_plan *pl, int dir)
 static SweepBatchFn pick_batch_fn(bool fp32, int P, int mm, bool diry)
 {
     if (fp32) {
+        if (P == 1) return pick_sweep_batch_f1(mm, diry);
         if (P == 2) return pick_sweep_batch_f2(mm, diry);
         if (P == 3) return pick_sweep_batch_f3(mm, diry);
     } else {
+        if (P == 1) return pick_sweep_batch_d1(mm, diry);
         if (P == 2) return pick_sweep_batch_d2(mm, diry);
         if (P == 3) return pick_sweep_batch_d3(mm, diry);
     }
@@ -109,9 +113,11 @@ static iga_status build_params(const iga_plan *pl, int dir, const SweepJob *jobs
 static WSweepFn pick_wfn(bool fp32, int P, int mm, bool diry)
 {
     if (fp32) {
+        if (P == 1) return pick_wsweep_f1(mm, diry);
         if (P == 2) return pick_wsweep_f2(mm, diry);
         if (P == 3) return pick_wsweep_f3(mm, diry);
     } else {
+        if (P == 1) return pick_wsweep_d1(mm, diry);
         if (P == 2) return pick_wsweep_d2(mm, diry);
         if (P == 3) return pick_wsweep_d3(mm, diry);
     }
@@ -121,9 +127,11 @@ static WSweepFn pick_wfn(bool fp32, int P, int mm, bool diry)
 static WSweepBatchFn pick_wbatch_fn(bool fp32, int P, int mm, bool diry)
 {
     if (fp32) {
+        if (P == 1) return pick_wsweep_batch_f1(mm, diry);
         if (P == 2) return pick_wsweep_batch_f2(mm, diry);
         if (P == 3) return pick_wsweep_batch_f3(mm, diry);
     } else {
+        if (P == 1) return pick_wsweep_batch_d1(mm, diry);
         if (P == 2) return pick_wsweep_batch_d2(mm, diry);
         if (P == 3) return pick_wsweep_batch_d3(mm, diry);
     }

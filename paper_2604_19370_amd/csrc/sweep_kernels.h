@@ -587,6 +587,10 @@ template <typename T, int P> static SweepBatchFn pick_mm_batch(int mm, bool diry
     return nullptr;
 }
 
+SweepFn pick_sweep_f1(int mm, bool diry);
+SweepFn pick_sweep_d1(int mm, bool diry);
+SweepBatchFn pick_sweep_batch_f1(int mm, bool diry);
+SweepBatchFn pick_sweep_batch_d1(int mm, bool diry);
 SweepFn pick_sweep_f2(int mm, bool diry);
 SweepFn pick_sweep_f3(int mm, bool diry);
 SweepFn pick_sweep_d2(int mm, bool diry);

@@ -462,6 +462,10 @@ template <typename T, int P> static WSweepBatchFn pick_wmm_batch(int mm, bool di
     return nullptr;
 }
 
+WSweepFn pick_wsweep_f1(int mm, bool diry);
+WSweepFn pick_wsweep_d1(int mm, bool diry);
+WSweepBatchFn pick_wsweep_batch_f1(int mm, bool diry);
+WSweepBatchFn pick_wsweep_batch_d1(int mm, bool diry);
 WSweepFn pick_wsweep_f2(int mm, bool diry);
 WSweepFn pick_wsweep_f3(int mm, bool diry);
 WSweepFn pick_wsweep_d2(int mm, bool diry);

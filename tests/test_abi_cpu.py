@@ -34,7 +34,7 @@ def test_default_coeffs_match_the_parameter_table():
     assert abs(a["c_react"] * 300 + a["c_forcing"] - a["c_rad"] * 300 ** 4) < 1e-10
 
 
-@pytest.mark.parametrize("field,value", [("p", 1), ("p", 4), ("nel_x", 4), ("nel_y", 2),
+@pytest.mark.parametrize("field,value", [("p", 0), ("p", 4), ("nel_x", 4), ("nel_y", 2),
                                          ("dt", 0.0), ("dt", -1.0), ("len_x", 0.0),
                                          ("scheme", 7), ("precision", 3), ("check_every", -1)])
 def test_plan_create_rejects_bad_descriptors(field, value):

@@ -48,6 +48,9 @@ CASES = [
     (71, 40, 3, "strang"),
     (5, 5, 2, "pr"),       # minimum mesh nel = 2p+1
     (7, 9, 3, "strang"),   # minimum mesh for p=3
+    (33, 27, 1, "pr"),     # linear B-splines (band 3)
+    (90, 51, 1, "strang"),
+    (3, 3, 1, "strang"),   # minimum mesh for p=1
 ]
 
 
@@ -68,7 +71,7 @@ def test_line_solve_fp64(nx, ny, p, scheme, dir, which):
 @pytest.mark.parametrize("lines", [1, 2, 4, 8, 16])
 @pytest.mark.parametrize("wpl", [0, 2, 4, 8])
 @pytest.mark.parametrize("n", [150, 600])
-@pytest.mark.parametrize("p", [2, 3])
+@pytest.mark.parametrize("p", [1, 2, 3])
 def test_line_solve_every_schedule(dir, lines, wpl, n, p):
     print(f"schedule dir{dir} lines{lines} wpl{wpl} n{n} p{p}", flush=True)
     sc = inputs.small_case(7, n, n - 17, p, "strang")
@@ -90,7 +93,7 @@ def test_line_solve_every_schedule(dir, lines, wpl, n, p):
 @pytest.mark.parametrize("lines", [1, 2, 4, 16])
 @pytest.mark.parametrize("mm", [9, 13, 17, 25, 33])
 @pytest.mark.parametrize("n", [150, 600])
-@pytest.mark.parametrize("p", [2, 3])
+@pytest.mark.parametrize("p", [1, 2, 3])
 def test_line_solve_every_window_schedule(dir, lines, mm, n, p):
     """Windowed solves (zero-state restarts `warmup` rows outside each chunk)
     against the oracle's banded LU, for every compiled rows-per-lane."""
@@ -98,7 +101,7 @@ def test_line_solve_every_window_schedule(dir, lines, mm, n, p):
     sc = inputs.small_case(8, n, n - 17, p, "strang")
     for precision, tol in (("fp64", TOL64), ("fp32", TOL32)):
         pl, od = plan_and_oracle(sc, precision)
-        if p == 2:
+        if p <= 2:
             assert pl.solver(dir)["warmup"] > 0
         try:
             pl.set_window_schedule(dir, lines, mm)
