@@ -20,7 +20,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "oracle.c")
 _LIB_PATH = os.path.join(_HERE, "liboracle.so")
 
-PR, STRANG = 0, 1
+PR, STRANG, EXPLICIT = 0, 1, 2
 WIND_CONST, WIND_SINCOS = 0, 1
 
 _COEFF_NAMES = ("c_adv", "c_diff", "c_react", "c_nld", "c_ign", "t_ig", "fuel_thr",
@@ -109,7 +109,7 @@ def make_desc(nel_x, nel_y, p, len_x, len_y, dt, scheme, coeffs=None, wind=None)
     d = Desc()
     d.nel_x, d.nel_y, d.p = int(nel_x), int(nel_y), int(p)
     d.len_x, d.len_y, d.dt = float(len_x), float(len_y), float(dt)
-    d.scheme = {"pr": PR, "strang": STRANG}.get(scheme, scheme)
+    d.scheme = {"pr": PR, "strang": STRANG, "explicit": EXPLICIT}.get(scheme, scheme)
     co = default_coeffs()
     if coeffs:
         co.update(coeffs)

@@ -14,6 +14,12 @@
  * Kronecker-product solves eq. (matrixPR) and eq. (matrixCN): x-lines first,
  * then y-lines.  No sum factorisation, no fusion, no reordering.
  *
+ * Three schemes: Peaceman-Rachford (Section 3.1), Strang splitting with
+ * Crank-Nicolson substeps (Section 3.2), and the explicit L2-projection step
+ * the paper uses as its accuracy baseline for eq. (linear) in Section 6.1:
+ * every term of the equation evaluated at T^n and weighted by tau, then the
+ * (Mx (x) My) solve -- the compute_rhs listing of Section 7 read as one step.
+ *
  * Readings of points the paper leaves open (all FP64):
  *  - F is evaluated from the state entering each substep (PR: T^n then
  *    T^{n+1/2}; Strang: S1 from T^n with weight tau/2, S3 from T** with weight
@@ -234,10 +240,12 @@ int oracle_mat1d(int n, int p, double L, int kind, double *band)
  *   x (with reaction): A = (1 - g C_react) M + g (C_diff K + C_adv bbar_x G)
  *   y:                 A = M + g (C_diff K + C_adv bbar_y G)
  * and the explicit counterpart B (signs of the g terms flipped), where
- * g = tau/2 (PR, both directions; Strang y) or tau/4 (Strang x). */
+ * g = tau/2 (PR, both directions; Strang y) or tau/4 (Strang x).  The explicit
+ * scheme inverts the mass matrices only: g = 0, A = B = M. */
 static void operator_gamma(const oracle_desc *d, int dir, double *g, double *react)
 {
     if (d->scheme == ORACLE_PR) *g = 0.5 * d->dt;
+    else if (d->scheme == ORACLE_EXPLICIT) *g = 0.0;
     else *g = (dir == 0) ? 0.25 * d->dt : 0.5 * d->dt;
     *react = (dir == 0) ? d->c.c_react : 0.0;
 }
@@ -388,9 +396,12 @@ static void wind_at(const oracle_desc *d, double x, double y, double *bx, double
 
 /* Weak form of one substep with explicit F, in the variables of eq.
  * (varPR_wildfire) and eq. (varCN):
- *   R_ij = sum_e sum_q w |J| [ S v - alpha ( C_diff d_eS d_ev + C_adv bbar_e d_eS v
- *                                            - [e = x] C_react S v )
+ *   R_ij = sum_e sum_q w |J| [ S v - ax ( C_diff S_x v_x + C_adv bbar_x S_x v - C_react S v )
+ *                                  - ay ( C_diff S_y v_y + C_adv bbar_y S_y v )
  *                              + beta ( f v - C_nld S^3 grad S . grad v ) ]
+ * where ax, ay weigh the explicit linear part of L1 (x, with the reaction)
+ * and L2 (y): one of them is zero in a PR or Strang substep, both are tau in
+ * the explicit scheme,
  *   f = -C_adv (b - bbar).grad S + C_forcing - C_rad S^4
  *       + [S > T_ig and fuel > thr] C_ign S exp(-T_act / S)
  * and, when rhs_fuel is given, the fuel right-hand side of the compute_rhs
@@ -403,7 +414,7 @@ typedef struct {
     unsigned char *flags;   /* [nel_x][nel_y], set to 1, never cleared */
 } ambiguity;
 
-static int assemble_quadrature(const oracle_desc *d, int edir, double alpha,
+static int assemble_quadrature(const oracle_desc *d, double ax, double ay,
                                double beta, const double *T, const double *fuel,
                                double *rhs_T, double *rhs_fuel, const ambiguity *amb)
 {
@@ -413,8 +424,6 @@ static int assemble_quadrature(const oracle_desc *d, int edir, double alpha,
     if (dir_init(&X, d->nel_x, p, d->len_x)) return 1;
     if (dir_init(&Y, d->nel_y, p, d->len_y)) { dir_free(&X); return 1; }
     const oracle_coeffs *c = &d->c;
-    double bbar_e = edir ? d->bbar_y : d->bbar_x;
-    double react_e = edir ? 0.0 : c->c_react;
     memset(rhs_T, 0, sizeof(double) * (size_t)Nx * Ny);
     if (rhs_fuel) memset(rhs_fuel, 0, sizeof(double) * (size_t)Nx * Ny);
 
@@ -451,16 +460,15 @@ static int assemble_quadrature(const oracle_desc *d, int edir, double alpha,
                         double f = -c->c_adv * ((bxv - d->bbar_x) * Sx + (byv - d->bbar_y) * Sy)
                                    + c->c_forcing - c->c_rad * S2 * S2 + c->c_ign * arr;
                         double g = c->c_nld * S2 * S;
-                        double dSe = edir ? Sy : Sx;
                         for (int a = 0; a <= p; ++a)
                             for (int b = 0; b <= p; ++b) {
                                 double v = vx[a] * vy[b];
                                 double v_x = dx[a] * vy[b];
                                 double v_y = vx[a] * dy[b];
-                                double dve = edir ? v_y : v_x;
                                 double val = S * v
-                                    - alpha * (c->c_diff * dSe * dve + c->c_adv * bbar_e * dSe * v
-                                               - react_e * S * v)
+                                    - ax * (c->c_diff * Sx * v_x + c->c_adv * d->bbar_x * Sx * v
+                                            - c->c_react * S * v)
+                                    - ay * (c->c_diff * Sy * v_y + c->c_adv * d->bbar_y * Sy * v)
                                     + beta * (f * v - g * (Sx * v_x + Sy * v_y));
                                 size_t k = (size_t)(ex + a) * Ny + (ey + b);
                                 rhs_T[k] += w * val;
@@ -477,23 +485,29 @@ static int assemble_quadrature(const oracle_desc *d, int edir, double alpha,
     return 0;
 }
 
-/* Substep parameters: explicit linear direction and the weights alpha (of the
- * explicit linear part) and beta (of F). */
-static int substep_params(const oracle_desc *d, int substep, int *edir,
-                          double *alpha, double *beta)
+/* Substep parameters: the weights ax, ay of the explicit linear parts of L1
+ * and L2, and beta of F. */
+static int substep_params(const oracle_desc *d, int substep, double *ax, double *ay,
+                          double *beta)
 {
     if (d->scheme == ORACLE_PR) {
         if (substep < 0 || substep > 1) return 1;
         /* substep 0: x implicit, L2 explicit; substep 1: y implicit, L1 explicit */
-        *edir = substep == 0 ? 1 : 0;
-        *alpha = 0.5 * d->dt;
+        *ax = substep == 0 ? 0.0 : 0.5 * d->dt;
+        *ay = substep == 0 ? 0.5 * d->dt : 0.0;
         *beta = 0.5 * d->dt;
+        return 0;
+    }
+    if (d->scheme == ORACLE_EXPLICIT) {
+        /* eq. (linear), every term at T^n with weight tau */
+        if (substep != 0) return 1;
+        *ax = *ay = *beta = d->dt;
         return 0;
     }
     if (substep != 0 && substep != 2) return 1;
     /* Strang S1 / S3: Crank-Nicolson on P1 over tau/2 */
-    *edir = 0;
-    *alpha = 0.25 * d->dt;
+    *ax = 0.25 * d->dt;
+    *ay = 0.0;
     *beta = 0.5 * d->dt;
     return 0;
 }
@@ -502,7 +516,8 @@ static int valid_desc(const oracle_desc *d)
 {
     return d && d->p >= 1 && d->p <= 3 && d->nel_x >= 1 && d->nel_y >= 1 &&
            d->len_x > 0 && d->len_y > 0 && d->dt > 0 &&
-           (d->scheme == ORACLE_PR || d->scheme == ORACLE_STRANG);
+           (d->scheme == ORACLE_PR || d->scheme == ORACLE_STRANG ||
+            d->scheme == ORACLE_EXPLICIT);
 }
 
 int oracle_assemble(const oracle_desc *d, int substep, const double *T,
@@ -522,10 +537,9 @@ int oracle_assemble(const oracle_desc *d, int substep, const double *T,
         free(band);
         return rc;
     }
-    int edir;
-    double alpha, beta;
-    if (substep_params(d, substep, &edir, &alpha, &beta)) return 1;
-    return assemble_quadrature(d, edir, alpha, beta, T, fuel, rhs_T, rhs_fuel, NULL);
+    double ax, ay, beta;
+    if (substep_params(d, substep, &ax, &ay, &beta)) return 1;
+    return assemble_quadrature(d, ax, ay, beta, T, fuel, rhs_T, rhs_fuel, NULL);
 }
 
 static int assemble_checked(const oracle_desc *d, int substep, const double *T,
@@ -534,10 +548,9 @@ static int assemble_checked(const oracle_desc *d, int substep, const double *T,
 {
     if (!amb || (d->scheme == ORACLE_STRANG && substep == 1))
         return oracle_assemble(d, substep, T, fuel, rhs_T, rhs_fuel);
-    int edir;
-    double alpha, beta;
-    if (substep_params(d, substep, &edir, &alpha, &beta)) return 1;
-    return assemble_quadrature(d, edir, alpha, beta, T, fuel, rhs_T, rhs_fuel, amb);
+    double ax, ay, beta;
+    if (substep_params(d, substep, &ax, &ay, &beta)) return 1;
+    return assemble_quadrature(d, ax, ay, beta, T, fuel, rhs_T, rhs_fuel, amb);
 }
 
 /* (A (x) B) X = R: solve A along the x-lines, then B along the y-lines. */
@@ -563,6 +576,11 @@ static int step_impl(const oracle_desc *d, double *T, double *fuel, const ambigu
         if (!rc) memcpy(T, R, sizeof(double) * n);
         if (!rc) rc = assemble_checked(d, 1, T, fuel, R, NULL, amb);
         if (!rc) rc = kron_solve(d, 1, 0, R);
+        if (!rc) memcpy(T, R, sizeof(double) * n);
+    } else if (d->scheme == ORACLE_EXPLICIT) {
+        /* (Mx (x) My) T^{n+1} = R(T^n, fuel^n) */
+        rc = assemble_checked(d, 0, T, fuel, R, RF, amb);
+        if (!rc) rc = kron_solve(d, 1, 1, R);
         if (!rc) memcpy(T, R, sizeof(double) * n);
     } else {
         /* eq. (matrixCN): T^n -> T* -> T** -> T^{n+1} */

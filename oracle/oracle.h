@@ -27,14 +27,14 @@ typedef struct {
     double c_forcing, c_rad, fuel_rate;
 } oracle_coeffs;
 
-enum { ORACLE_PR = 0, ORACLE_STRANG = 1 };
+enum { ORACLE_PR = 0, ORACLE_STRANG = 1, ORACLE_EXPLICIT = 2 };
 enum { ORACLE_WIND_CONST = 0, ORACLE_WIND_SINCOS = 1 };
 
 typedef struct {
     int nel_x, nel_y, p;
     double len_x, len_y;      /* physical edge lengths (m) */
     double dt;                /* tau */
-    int scheme;               /* ORACLE_PR or ORACLE_STRANG */
+    int scheme;               /* ORACLE_PR, ORACLE_STRANG or ORACLE_EXPLICIT */
     oracle_coeffs c;
     /* wind b(x,y): CONST  -> (bx, by)
      *              SINCOS -> (bx + ax sin(2 pi y/len_y), by + ay cos(2 pi x/len_x))
@@ -60,7 +60,8 @@ int oracle_basis_eval(int n, int p, double L, int deriv, const double *xs,
 int oracle_mat1d(int n, int p, double L, int kind, double *band);
 /* The banded 1D operator the scheme inverts along direction dir (0 = x,
  * 1 = y): which 0 = implicit operator A, 1 = mass matrix M, 2 = explicit
- * Crank-Nicolson operator B of the Strang middle substep. */
+ * Crank-Nicolson operator B of the Strang middle substep (the explicit scheme:
+ * A = B = M). */
 int oracle_operator(const oracle_desc *d, int dir, int which, double *band);
 /* Solve band * x = b for `nrhs` right-hand sides stored with stride `stride`
  * between successive rows and `dist` between right-hand sides (no pivoting). */
@@ -69,7 +70,8 @@ int oracle_band_solve(int N, int p, const double *band, double *x, int nrhs,
 /* Line solve on a 2D field: op^{-1} along direction dir on every line
  * (which as in oracle_operator; which 2 applies A^{-1} B). */
 int oracle_line_solve(const oracle_desc *d, int dir, int which, double *X);
-/* Quadrature right-hand side of one substep (PR: 0, 1; Strang: 0, 1, 2).
+/* Quadrature right-hand side of one substep (PR: 0, 1; Strang: 0, 1, 2;
+ * explicit: 0).
  * rhs_fuel (may be NULL) receives the fuel right-hand side of the step. */
 int oracle_assemble(const oracle_desc *d, int substep, const double *T,
                     const double *fuel, double *rhs_T, double *rhs_fuel);

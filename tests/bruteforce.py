@@ -108,7 +108,9 @@ def directional(d, dirn, which):
     n = d["nel_y"] if dirn else d["nel_x"]
     L = d["len_y"] if dirn else d["len_x"]
     M, K, G = mats_1d(n, d["p"], L)
-    if d["scheme"] == "pr":
+    if d["scheme"] == "explicit":
+        g = 0.0
+    elif d["scheme"] == "pr":
         g = 0.5 * d["dt"]
     else:
         g = 0.25 * d["dt"] if dirn == 0 else 0.5 * d["dt"]
@@ -127,9 +129,47 @@ def kron_solve(A, B, R):
     return np.linalg.solve(np.kron(A, B), R.reshape(n)).reshape(R.shape)
 
 
+def explicit_rhs(d, T, fuel):
+    """Right-hand side of the explicit L2-projection step written straight
+    from the equation (no split of the operator, the full wind b): per
+    quadrature point  S v + tau [ -C_diff grad S . grad v - C_adv (b . grad S) v
+    + C_react S v + (C_forcing - C_rad S^4 + C_ign [ign] S e^{-T_act/S}) v
+    - C_nld S^3 grad S . grad v ],  and the fuel  Fu v - tau rate [ign] S e^{-T_act/S} Fu v."""
+    p, tau = d["p"], d["dt"]
+    xq, wx = quad_1d(d["nel_x"], d["len_x"], p + 1)
+    yq, wy = quad_1d(d["nel_y"], d["len_y"], p + 1)
+    Vx, Dx = basis(d["nel_x"], p, d["len_x"], xq), basis(d["nel_x"], p, d["len_x"], xq, 1)
+    Vy, Dy = basis(d["nel_y"], p, d["len_y"], yq), basis(d["nel_y"], p, d["len_y"], yq, 1)
+    # 2D basis tables: rows = quadrature points, columns = dofs (i, j)
+    Phi = np.einsum("ai,bj->abij", Vx, Vy).reshape(xq.size * yq.size, -1)
+    Phx = np.einsum("ai,bj->abij", Dx, Vy).reshape(xq.size * yq.size, -1)
+    Phy = np.einsum("ai,bj->abij", Vx, Dy).reshape(xq.size * yq.size, -1)
+    W = np.outer(wx, wy).ravel()
+    S, Sx, Sy, Fu = Phi @ T.ravel(), Phx @ T.ravel(), Phy @ T.ravel(), Phi @ fuel.ravel()
+    X, Y = np.meshgrid(xq, yq, indexing="ij")
+    X, Y = X.ravel(), Y.ravel()
+    if d["wind_kind"] == "sincos":
+        bx = d["bx"] + d["ax"] * np.sin(2 * np.pi * Y / d["len_y"])
+        by = d["by"] + d["ay"] * np.cos(2 * np.pi * X / d["len_x"])
+    else:
+        bx, by = np.full_like(X, d["bx"]), np.full_like(X, d["by"])
+    ign = (S > d["t_ig"]) & (Fu > d["fuel_thr"])
+    arr = np.zeros_like(S)
+    arr[ign] = S[ign] * np.exp(-d["t_act"] / S[ign])
+    flux = -(d["c_diff"] + d["c_nld"] * S ** 3)          # coefficient of grad S . grad v
+    src = (-d["c_adv"] * (bx * Sx + by * Sy) + d["c_react"] * S + d["c_forcing"]
+           - d["c_rad"] * S ** 4 + d["c_ign"] * arr)     # coefficient of v
+    R = Phi.T @ (W * (S + tau * src)) + Phx.T @ (W * tau * flux * Sx) + Phy.T @ (W * tau * flux * Sy)
+    RF = Phi.T @ (W * (Fu - tau * d["fuel_rate"] * arr * Fu))
+    return R.reshape(T.shape), RF.reshape(T.shape)
+
+
 def step(d, T, fuel):
     """One full step with dense Kronecker matrices and numpy.linalg.solve."""
     Mx, My = directional(d, 0, 1), directional(d, 1, 1)
+    if d["scheme"] == "explicit":
+        R, RF = explicit_rhs(d, T, fuel)
+        return kron_solve(Mx, My, R), kron_solve(Mx, My, RF)
     Ax, Ay = directional(d, 0, 0), directional(d, 1, 0)
     if d["scheme"] == "pr":
         R, RF = rhs(d, T, fuel, 1, 0.5 * d["dt"], 0.5 * d["dt"], with_fuel=True)

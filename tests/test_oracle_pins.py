@@ -285,7 +285,7 @@ def test_strang_middle_rhs_is_kronecker_matvec():
 # whole steps
 # ---------------------------------------------------------------------------
 @pytest.mark.parametrize("p", [1, 2, 3])
-@pytest.mark.parametrize("scheme", ["pr", "strang"])
+@pytest.mark.parametrize("scheme", ["pr", "strang", "explicit"])
 def test_step_matches_dense_bruteforce(p, scheme):
     sc = inputs.small_case(11, 6, 5, p, scheme, dt=3e-3)
     d = oracle.desc_from_scenario(sc)
@@ -297,7 +297,7 @@ def test_step_matches_dense_bruteforce(p, scheme):
     assert (Fn != sc.fuel0).any()  # some points ignited, so fuel moved
 
 
-@pytest.mark.parametrize("scheme", ["pr", "strang"])
+@pytest.mark.parametrize("scheme", ["pr", "strang", "explicit"])
 def test_ambient_is_fixed_point(scheme):
     sc = inputs.small_case(5, 12, 9, 2, scheme, dt=5e-3, wind=inputs.Wind("const", 1.2, -0.4))
     d = oracle.desc_from_scenario(sc)
@@ -308,7 +308,7 @@ def test_ambient_is_fixed_point(scheme):
 
 
 @pytest.mark.parametrize("p", [1, 2, 3])
-@pytest.mark.parametrize("scheme", ["pr", "strang"])
+@pytest.mark.parametrize("scheme", ["pr", "strang", "explicit"])
 def test_constant_field_preserved_without_sources(p, scheme):
     d = oracle.make_desc(9, 7, p, 9.0, 7.0, 0.05, scheme, coeffs=SOURCES_OFF,
                          wind=dict(kind="const", bx=2.0, by=-1.0))
@@ -317,11 +317,11 @@ def test_constant_field_preserved_without_sources(p, scheme):
     assert np.abs(Tn - 517.0).max() < 1e-10
 
 
-@pytest.mark.parametrize("scheme", ["pr", "strang"])
-def test_mass_conserved_with_nonlinear_diffusion(scheme):
+@pytest.mark.parametrize("scheme,tau", [("pr", 0.2), ("strang", 0.2), ("explicit", 0.02)])
+def test_mass_conserved_with_nonlinear_diffusion(scheme, tau):
     """No sources, no wind: sum_ij m_i m_j T_ij = int T is conserved, even with
     the T^3 grad T flux (its weak form vanishes against v = 1)."""
-    d = oracle.make_desc(10, 8, 2, 10.0, 8.0, 0.2, scheme,
+    d = oracle.make_desc(10, 8, 2, 10.0, 8.0, tau, scheme,
                          coeffs=dict(c_ign=0.0, c_forcing=0.0, c_rad=0.0, c_react=0.0,
                                      c_nld=1e-10, c_diff=0.7),
                          wind=dict(kind="const", bx=0.0, by=0.0))
@@ -336,13 +336,14 @@ def test_mass_conserved_with_nonlinear_diffusion(scheme):
 
 
 @pytest.mark.parametrize("p", [1, 2, 3])
-@pytest.mark.parametrize("scheme", ["pr", "strang"])
+@pytest.mark.parametrize("scheme", ["pr", "strang", "explicit"])
 @pytest.mark.parametrize("react", [0.0, -0.4])
 def test_amplification_factor_of_discrete_eigenmodes(p, scheme, react):
     """Pure diffusion (+ linear reaction in L1): T = phi_k (x) phi_l with
     K phi = lambda M phi is multiplied per step by
-      PR:     (1 - tau mu_y/2)(1 - tau nu_x/2) / ((1 + tau nu_x/2)(1 + tau mu_y/2))
-      Strang: ((1 - tau nu_x/4)/(1 + tau nu_x/4))^2 (1 - tau mu_y/2)/(1 + tau mu_y/2)
+      PR:       (1 - tau mu_y/2)(1 - tau nu_x/2) / ((1 + tau nu_x/2)(1 + tau mu_y/2))
+      Strang:   ((1 - tau nu_x/4)/(1 + tau nu_x/4))^2 (1 - tau mu_y/2)/(1 + tau mu_y/2)
+      explicit: 1 - tau (nu_x + mu_y)
     with mu = C_diff lambda, nu_x = mu_x - C_react."""
     nx, ny, tau, cd = 11, 9, 0.8, 0.6
     d = oracle.make_desc(nx, ny, p, 11.0, 9.0, tau, scheme,
@@ -360,6 +361,8 @@ def test_amplification_factor_of_discrete_eigenmodes(p, scheme, react):
         nu, mu = cd * lx[k] - react, cd * ly[l]
         if scheme == "pr":
             g = (1 - tau * mu / 2) * (1 - tau * nu / 2) / ((1 + tau * nu / 2) * (1 + tau * mu / 2))
+        elif scheme == "explicit":
+            g = 1 - tau * (nu + mu)
         else:
             g = ((1 - tau * nu / 4) / (1 + tau * nu / 4)) ** 2 * (1 - tau * mu / 2) / (1 + tau * mu / 2)
         Tn, _ = oracle.step(d, T, np.ones_like(T))
@@ -393,7 +396,7 @@ def test_projected_cosine_mode_decays_at_continuous_rate(scheme):
         assert rel(Tn, g * T) < 3e-5   # a factor-of-two slip in tau/2 would give ~1e-2
 
 
-@pytest.mark.parametrize("scheme", ["pr", "strang"])
+@pytest.mark.parametrize("scheme", ["pr", "strang", "explicit"])
 def test_reflection_symmetry(scheme):
     """x -> L - x with b_x -> -b_x maps solutions onto solutions (constant wind)."""
     sc = inputs.small_case(21, 9, 7, 2, scheme, dt=4e-3, wind=inputs.Wind("const", 0.9, 0.4))
@@ -455,7 +458,7 @@ def test_eval_grid_and_burned_fraction():
     assert 3 / 8 <= bfrac <= 5 / 8
 
 
-@pytest.mark.parametrize("scheme", ["pr", "strang"])
+@pytest.mark.parametrize("scheme", ["pr", "strang", "explicit"])
 def test_step_flagged_marks_ambiguous_ignition_decisions(scheme):
     """The flagged step returns the plain step's result and marks exactly the
     elements where some quadrature point's ignition decision is within the
