@@ -1,0 +1,103 @@
+"""The verification problem of Section 5 ("ring of fire") on the HIP library.
+
+Zero wind, fuel 1, a smooth central ball of heat on [0, 100]^2 with the
+paper's 100^2 mesh, p = 1, 2, 3, both schemes:
+
+- FP64: the first steps match the oracle per step (1e-12), the graph-replayed
+  run to t = 1 (200 steps) matches the oracle's 200 steps, and the state stays
+  mirror-symmetric (x -> 100 - x, y -> 100 - y) to rounding;
+- FP32 + refinement: after 200 steps the burned region equals the oracle's up
+  to a sliver along the front and stays mirror-symmetric to the same extent
+  (the float rounding is not mirror-symmetric, and ignition decisions within
+  rounding of a threshold can fall either way).
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2604_19370_amd import iga, inputs
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+GRID = np.linspace(0.0, 100.0, 401)
+
+
+def dev(a, dtype):
+    return torch.tensor(np.ascontiguousarray(a), dtype=dtype, device="cuda")
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.double().cpu().numpy()
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def mirror_gap(A):
+    s = np.abs(A).max()
+    return max(np.abs(A - A[::-1]).max(), np.abs(A - A[:, ::-1]).max()) / s
+
+
+def burned(od, F):
+    return oracle.eval_grid(od, F, GRID, GRID) < 0.5
+
+
+def run_graph(pl, T, F, steps):
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        pl.run(T, F, steps, stream)
+    torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("p", [1, 2, 3])
+@pytest.mark.parametrize("scheme", ["pr", "strang"])
+def test_ring_of_fire_fp64(p, scheme):
+    sc = inputs.ring_of_fire(100, p, scheme)
+    print(f"ring of fire fp64 {sc.name}", flush=True)
+    pl = iga.Plan.from_scenario(sc, precision="fp64")
+    pl.factor()
+    od = oracle.desc_from_scenario(sc)
+    T, F = dev(sc.T0, torch.float64), dev(sc.fuel0, torch.float64)
+    for k in range(3):
+        Tp, Fp = host(T), host(F)
+        pl.step(T, F)
+        To, Fo = oracle.step(od, Tp, Fp)
+        eT, eF = rel(host(T), To), rel(host(F), Fo)
+        assert eT < 1e-12 and eF < 1e-12, (k, eT, eF)
+    Tp, Fp = host(T), host(F)
+    run_graph(pl, T, F, sc.steps - 3)
+    To, Fo = oracle.run(od, Tp, Fp, sc.steps - 3)
+    Tg, Fg = host(T), host(F)
+    eT, eF = rel(Tg, To), rel(Fg, Fo)
+    gT, gF = mirror_gap(Tg), mirror_gap(Fg)
+    print(f"after {sc.steps} steps: vs oracle T {eT:.2e} F {eF:.2e}; mirror gap T {gT:.2e} "
+          f"F {gF:.2e}; burned fraction {burned(od, Fg).mean():.4f}", flush=True)
+    assert eT < 1e-9 and eF < 1e-9
+    assert gT < 1e-10 and gF < 1e-10
+    pl.close()
+
+
+@pytest.mark.parametrize("scheme", ["pr", "strang"])
+def test_ring_of_fire_fp32(scheme):
+    sc = inputs.ring_of_fire(100, 2, scheme)
+    print(f"ring of fire fp32 {sc.name}", flush=True)
+    pl = iga.Plan.from_scenario(sc, precision="fp32")
+    pl.factor()
+    od = oracle.desc_from_scenario(sc)
+    T, F = dev(sc.T0, torch.float32), dev(sc.fuel0, torch.float32)
+    run_graph(pl, T, F, sc.steps)
+    To, Fo = oracle.run(od, sc.T0, sc.fuel0, sc.steps)
+    Tg, Fg = host(T), host(F)
+    bg, bo = burned(od, Fg), burned(od, Fo)
+    mism, mirror = (bg != bo).sum() / bo.sum(), (bg != bg[::-1]).sum() / bg.sum()
+    eT, gT = rel(Tg, To), mirror_gap(Tg)
+    print(f"after {sc.steps} steps: vs oracle T {eT:.2e}, burned mismatch {mism:.2e}, "
+          f"mirror gap T {gT:.2e}, burned mirror mismatch {mirror:.2e}", flush=True)
+    assert np.isfinite(Tg).all() and np.isfinite(Fg).all()
+    assert eT < 1e-3
+    assert mism < 0.01 and mirror < 0.01
+    pl.close()
