@@ -54,7 +54,13 @@ typedef enum {
     IGA_ESTATE = 6        /* call out of order (e.g. step before factor)    */
 } iga_status;
 
-typedef enum { IGA_PR = 0, IGA_STRANG_CN = 1 } iga_scheme;
+/* IGA_PR: Peaceman-Rachford alternating directions (Section 3.1).
+ * IGA_STRANG_CN: Strang splitting with Crank-Nicolson substeps (Section 3.2).
+ * IGA_EXPLICIT: the explicit L2-projection step the paper compares against
+ * for eq. (linear) in Section 6.1 (the compute_rhs listing of Section 7 taken
+ * as one step): every term at T^n with weight tau, then (M^x (x) M^y)^{-1}.
+ * Only conditionally stable. */
+typedef enum { IGA_PR = 0, IGA_STRANG_CN = 1, IGA_EXPLICIT = 2 } iga_scheme;
 
 /* IGA_FP64: every kernel in double.
  * IGA_FP32_REFINE: state, right-hand sides and line solves in float with float
@@ -88,7 +94,7 @@ typedef struct {
 
 typedef struct {
     int32_t nel_x, nel_y;   /* elements per direction, >= 2p+1 and <= 65536     */
-    int32_t p;              /* B-spline degree, 2 or 3                            */
+    int32_t p;              /* B-spline degree, 1, 2 or 3                         */
     double len_x, len_y;    /* physical edge lengths (m), > 0                     */
     double dt;              /* time step tau (s), > 0                             */
     int32_t scheme;         /* iga_scheme                                         */
@@ -110,7 +116,7 @@ void iga_default_coeffs(iga_coeffs *out);
  * 1D matrices M, K, G (Section 3.1) and the directional operators of the
  * scheme, uploaded to the current HIP device.  Allocates device memory (tables
  * and scratch of about 2 fields).  *out is NULL on failure.
- * Errors: IGA_EINVAL (NULL pointers, p not in {2,3}, nel < 2p+1, lengths or dt
+ * Errors: IGA_EINVAL (NULL pointers, p not in {1,2,3}, nel < 2p+1, lengths or dt
  * not > 0, unknown enum), IGA_ENOMEM, IGA_EDEVICE. */
 iga_status iga_plan_create(const iga_plan_desc *desc, iga_plan **out);
 
@@ -130,15 +136,17 @@ iga_status iga_factor_1d(iga_plan *plan, void *stream);
 
 /* Quadrature right-hand side of one substep (weak forms eq. varPR_wildfire
  * and eq. varCN).  substep: PR 0 (x implicit) or 1 (y implicit); Strang 0 (S1)
- * or 2 (S3).  Reads T and fuel, writes rhs_T; when rhs_fuel is not NULL also
+ * or 2 (S3); explicit 0 (all terms, weight tau).  Reads T and fuel, writes
+ * rhs_T; when rhs_fuel is not NULL also
  * writes the fuel right-hand side fuel v - tau fuel_rate [ign] T exp(-t_act/T)
  * fuel v.  All four are fields (layout above); rhs buffers must not alias the
  * inputs.  The Strang middle substep has no quadrature right-hand side (it is
  * iga_line_solve(dir = 1, which = 2)): substep 1 of a Strang plan is
  * IGA_EINVAL.
  * IGA_FP32_REFINE plans return the increment form R - (A^x (x) M^y) T
- * (PR substep 1: R - (M^x (x) A^y) T; fuel: R_fuel - (M^x (x) M^y) fuel), whose
- * solve is the change of the state over the substep. */
+ * (PR substep 1: R - (M^x (x) A^y) T; explicit: R - (M^x (x) M^y) T; fuel:
+ * R_fuel - (M^x (x) M^y) fuel), whose solve is the change of the state over
+ * the substep. */
 iga_status iga_assemble_rhs(const iga_plan *plan, int32_t substep, const void *T,
                             const void *fuel, void *rhs_T, void *rhs_fuel, void *stream);
 
@@ -148,18 +156,20 @@ iga_status iga_assemble_rhs(const iga_plan *plan, int32_t substep, const void *T
  *   which 0: x <- A^{-1} x  with A the scheme's implicit operator in dir
  *            (PR: (1 - tau/2 c_react) M + tau/2 (c_diff K + c_adv bbar G) along
  *            x, M + tau/2 (...) along y; Strang: tau/4 and reaction along x,
- *            tau/2 along y);
+ *            tau/2 along y; explicit: A = M);
  *   which 1: x <- M^{-1} x;
  *   which 2: x <- A^{-1} B x with B the explicit Crank-Nicolson counterpart of
- *            A (signs of the tau terms flipped) -- the Strang middle substep.
+ *            A (signs of the tau terms flipped) -- the Strang middle substep
+ *            (explicit plans: B = M, so this is the identity up to rounding).
  * Requires iga_factor_1d. */
 iga_status iga_line_solve(const iga_plan *plan, int32_t dir, int32_t which, void *x,
                           void *stream);
 
 /* One full time step, in place on (T, fuel): PR = assemble, A^x (x) M^y solve,
  * assemble, M^x (x) A^y solve; Strang-CN = S1 (assemble, A^x (x) M^y), S2
- * (A^{-1} B along y), S3 (assemble, A^x (x) M^y); then the fuel update
- * (Mx (x) My)^{-1} R_fuel(T^n, fuel^n).  Requires iga_factor_1d. */
+ * (A^{-1} B along y), S3 (assemble, A^x (x) M^y); explicit = assemble,
+ * M^x (x) M^y solve; then the fuel update (Mx (x) My)^{-1} R_fuel(T^n, fuel^n).
+ * Requires iga_factor_1d. */
 iga_status iga_step(iga_plan *plan, void *T, void *fuel, void *stream);
 
 /* nsteps steps, in place, replayed from a HIP graph captured on first use for
@@ -224,7 +234,8 @@ iga_status iga_autotune(iga_plan *plan, const void *T, const void *fuel, int32_t
  * line sweeps) runs as one launch over all members per line-solve schedule
  * group (members with equal rows per lane, lines per workgroup and wavefronts
  * per line), so the per-step launch count does not grow with the member
- * count.  Each member's result is, up to rounding, the one its own plan
+ * count.  Explicit-scheme members take part in the first assembly and the
+ * first two sweeps only.  Each member's result is, up to rounding, the one its own plan
  * would compute with the same line-solve schedule (the batched kernels are
  * separately compiled and may contract multiply-adds differently).
  * ------------------------------------------------------------------------ */
@@ -239,7 +250,9 @@ iga_status iga_ensemble_create(const iga_plan_desc *members, int32_t n, iga_ense
 iga_status iga_ensemble_destroy(iga_ensemble *ens);
 iga_status iga_ensemble_size(const iga_ensemble *ens, int32_t *n);
 
-/* Kernel launches per step (2 assemblies + 2 x 2 sweeps per schedule group). */
+/* Kernel launches per step: 1 assembly + 1 sweep per schedule group and
+ * direction, and the same again over the members that have a second phase
+ * (every scheme but the explicit one). */
 iga_status iga_ensemble_launches(const iga_ensemble *ens, int32_t *per_step);
 
 /* One step of every member, in place: T[m], fuel[m] are member m's fields

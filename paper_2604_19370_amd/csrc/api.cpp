@@ -1,5 +1,5 @@
 // api.cpp -- the C ABI (include/iga.h): argument checking, the step
-// sequences of the two schemes, and the graph-replayed run loop.
+// sequences of the schemes, and the graph-replayed run loop.
 #include <cmath>
 #include <cstring>
 #include <new>
@@ -46,7 +46,8 @@ iga_status check_desc(const iga_plan_desc *d)
     if (!(d->len_x > 0) || !(d->len_y > 0) || !std::isfinite(d->len_x) || !std::isfinite(d->len_y))
         return fail(IGA_EINVAL, "lengths must be finite and > 0");
     if (!(d->dt > 0) || !std::isfinite(d->dt)) return fail(IGA_EINVAL, "dt must be finite and > 0");
-    if (d->scheme != IGA_PR && d->scheme != IGA_STRANG_CN) return fail(IGA_EINVAL, "unknown scheme");
+    if (d->scheme != IGA_PR && d->scheme != IGA_STRANG_CN && d->scheme != IGA_EXPLICIT)
+        return fail(IGA_EINVAL, "unknown scheme");
     if (d->precision != IGA_FP64 && d->precision != IGA_FP32_REFINE)
         return fail(IGA_EINVAL, "unknown precision");
     if (d->wind.kind != IGA_WIND_CONST && d->wind.kind != IGA_WIND_SINCOS)
@@ -69,8 +70,8 @@ iga_status check_field(const void *p, const char *name)
 // One step in place; the right-hand sides live in the plan's scratch buffers.
 // FP32 plans advance in increment form: the assembled right-hand sides are
 // R - (implicit operator) S, the solves give the increment, and the y sweep
-// adds the state it was taken from.  A step is six launches: assembly, x
-// sweep, y sweep, twice.
+// adds the state it was taken from.  A PR or Strang step is six launches:
+// assembly, x sweep, y sweep, twice; an explicit step is the first three.
 void step_phases(const iga_plan *pl, void *T, void *fuel, StepPhases &sp)
 {
     void *R = pl->scratch_r.ptr, *RF = pl->scratch_rf.ptr;
@@ -83,7 +84,15 @@ void step_phases(const iga_plan *pl, void *T, void *fuel, StepPhases &sp)
     const int zs = pl->delta ? 1 : 0;
     sp.a1 = AsmArgs{0, T, fuel, R, RF};
     sp.x1 = {{R, R, OP_AX, -1, -1, nullptr, 0}, {RF, RF, OP_MX, -1, -1, nullptr, 0, zs}};
-    if (pr) {
+    sp.two = true;
+    if (pl->d.scheme == IGA_EXPLICIT) {
+        // (M^x (x) M^y) solves of both right-hand sides, in the same launches
+        sp.x1[0].op0 = OP_MX;
+        sp.y1 = {{R, T, OP_MY, -1, -1, bT, 0}, {RF, fuel, OP_MY, -1, -1, bF, 0, zs}};
+        sp.two = false;
+        sp.x2.clear();
+        sp.y2.clear();
+    } else if (pr) {
         sp.y1 = {{R, T, OP_MY, -1, -1, bT, 0}};
         // substep 2: y implicit
         sp.a2 = AsmArgs{1, T, fuel, R, nullptr};
@@ -110,6 +119,7 @@ static iga_status step_impl(iga_plan *pl, void *T, void *fuel, hipStream_t s)
     };
     if ((st = launch_assemble(pl, sp.a1.substep, sp.a1.T, sp.a1.fuel, sp.a1.R, sp.a1.RF, s))) return st;
     if ((st = sweep(0, sp.x1)) || (st = sweep(1, sp.y1))) return st;
+    if (!sp.two) return IGA_OK;
     if ((st = launch_assemble(pl, sp.a2.substep, sp.a2.T, sp.a2.fuel, sp.a2.R, sp.a2.RF, s))) return st;
     if ((st = sweep(0, sp.x2)) || (st = sweep(1, sp.y2))) return st;
     return IGA_OK;
@@ -230,6 +240,8 @@ iga_status iga_assemble_rhs(const iga_plan *plan, int32_t substep, const void *T
         return fail(IGA_EINVAL, "right-hand sides must not alias the state");
     if (plan->d.scheme == IGA_PR) {
         if (substep != 0 && substep != 1) return fail(IGA_EINVAL, "PR substep must be 0 or 1");
+    } else if (plan->d.scheme == IGA_EXPLICIT) {
+        if (substep != 0) return fail(IGA_EINVAL, "explicit substep must be 0");
     } else if (substep != 0 && substep != 2) {
         return fail(IGA_EINVAL,
                     "Strang substep must be 0 or 2 (the middle substep is iga_line_solve(1, 2))");

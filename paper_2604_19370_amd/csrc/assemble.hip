@@ -357,6 +357,10 @@ static void make_params(const iga_plan *pl, int substep, const void *S, const vo
         if (substep == 0) { ky_e = h; kx_i = h; }
         else { kx_e = h; ky_i = h; }
         beta = h;
+    } else if (d.scheme == IGA_EXPLICIT) {
+        // eq. (linear): every term at T^n with weight tau; implicit part M (x) M
+        kx_e = ky_e = d.dt;
+        beta = d.dt;
     } else {
         // S1 / S3: Crank-Nicolson on L1 over tau/2 (explicit and implicit halves)
         kx_e = kx_i = 0.25 * d.dt;

@@ -3,7 +3,8 @@
 // two assemblies and four sweeps) is one batched launch over all members per
 // line-solve schedule group, so small members share the GPU instead of each
 // launching grids too small to fill it; run() replays the step loop from a
-// HIP graph.  Members are independent: no data moves between them.
+// HIP graph.  Members of the explicit scheme take part in the first three
+// phases only.  Members are independent: no data moves between them.
 #include <algorithm>
 
 #include "iga_internal.h"
@@ -19,6 +20,7 @@ struct iga_ensemble {
     bool bound = false;
     BatchLaunch a1, a2;
     std::vector<BatchLaunch> x1, y1, x2, y2;
+    bool two = false;   // some member has a second assembly and sweep pair
     GraphCache graph;
 
     ~iga_ensemble()
@@ -53,22 +55,30 @@ iga_status bind(iga_ensemble *e, void *const *T, void *const *F)
     if (e->bound && std::equal(T, T + n, e->T.begin()) && std::equal(F, F + n, e->F.begin()))
         return IGA_OK;
     e->unbind();
-    std::vector<AsmArgs> a1(n), a2(n);
-    std::vector<std::vector<SweepJob>> x1(n), y1(n), x2(n), y2(n);
+    std::vector<AsmArgs> a1(n), a2;
+    std::vector<std::vector<SweepJob>> x1(n), y1(n), x2, y2;
+    std::vector<iga_plan *> second;   // members with a second phase
     for (size_t m = 0; m < n; ++m) {
         StepPhases sp;
         step_phases(e->plans[m], T[m], F[m], sp);
         a1[m] = sp.a1;
-        a2[m] = sp.a2;
         x1[m] = sp.x1;
         y1[m] = sp.y1;
-        x2[m] = sp.x2;
-        y2[m] = sp.y2;
+        if (sp.two) {
+            second.push_back(e->plans[m]);
+            a2.push_back(sp.a2);
+            x2.push_back(sp.x2);
+            y2.push_back(sp.y2);
+        }
     }
     iga_status st;
-    if ((st = build_assemble_batch(e->plans, a1, e->a1)) || (st = build_assemble_batch(e->plans, a2, e->a2)) ||
-        (st = build_sweep_batch(e->plans, 0, x1, e->x1)) || (st = build_sweep_batch(e->plans, 1, y1, e->y1)) ||
-        (st = build_sweep_batch(e->plans, 0, x2, e->x2)) || (st = build_sweep_batch(e->plans, 1, y2, e->y2)))
+    if ((st = build_assemble_batch(e->plans, a1, e->a1)) ||
+        (st = build_sweep_batch(e->plans, 0, x1, e->x1)) || (st = build_sweep_batch(e->plans, 1, y1, e->y1)))
+        return st;
+    e->two = !second.empty();
+    if (e->two &&
+        ((st = build_assemble_batch(second, a2, e->a2)) || (st = build_sweep_batch(second, 0, x2, e->x2)) ||
+         (st = build_sweep_batch(second, 1, y2, e->y2))))
         return st;
     e->T.assign(T, T + n);
     e->F.assign(F, F + n);
@@ -88,8 +98,10 @@ iga_status launch_all(const std::vector<BatchLaunch> &v, hipStream_t s)
 iga_status step_bound(iga_ensemble *e, hipStream_t s)
 {
     iga_status st;
-    if ((st = launch_batch(e->a1, s)) || (st = launch_all(e->x1, s)) || (st = launch_all(e->y1, s)) ||
-        (st = launch_batch(e->a2, s)) || (st = launch_all(e->x2, s)) || (st = launch_all(e->y2, s)))
+    if ((st = launch_batch(e->a1, s)) || (st = launch_all(e->x1, s)) || (st = launch_all(e->y1, s)))
+        return st;
+    if (e->two &&
+        ((st = launch_batch(e->a2, s)) || (st = launch_all(e->x2, s)) || (st = launch_all(e->y2, s))))
         return st;
     return IGA_OK;
 }
@@ -130,10 +142,13 @@ iga_status set_window_all(iga_ensemble *e, int dir, int lines, int mm)
     return IGA_OK;
 }
 
-int groups(const iga_ensemble *e, int dir)
+// schedule groups of direction dir among all members (second = false) or
+// among the members with a second assembly and sweep pair (second = true)
+int groups(const iga_ensemble *e, int dir, bool second = false)
 {
     std::vector<Schedule> seen;
     for (const iga_plan *pl : e->plans) {
+        if (second && pl->d.scheme == IGA_EXPLICIT) continue;
         const Schedule &s = pl->sched[dir];
         bool found = false;
         for (const Schedule &t : seen)
@@ -198,7 +213,8 @@ iga_status iga_ensemble_size(const iga_ensemble *ens, int32_t *n)
 iga_status iga_ensemble_launches(const iga_ensemble *ens, int32_t *per_step)
 {
     if (!ens || !per_step) return fail(IGA_EINVAL, "NULL argument");
-    *per_step = 2 + 2 * groups(ens, 0) + 2 * groups(ens, 1);
+    const int g2 = groups(ens, 0, true) + groups(ens, 1, true);
+    *per_step = 1 + groups(ens, 0) + groups(ens, 1) + (g2 ? 1 + g2 : 0);
     return IGA_OK;
 }
 

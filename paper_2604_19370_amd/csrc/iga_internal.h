@@ -254,6 +254,7 @@ iga_status launch_nonfinite(const iga_plan *pl, const void *T, const void *fuel,
 struct StepPhases {
     AsmArgs a1, a2;
     std::vector<SweepJob> x1, y1, x2, y2;
+    bool two = true;   // false: the step is a1, x1, y1 only (explicit scheme)
 };
 void step_phases(const iga_plan *pl, void *T, void *fuel, StepPhases &sp);
 iga_status check_desc(const iga_plan_desc *d);

@@ -123,10 +123,12 @@ static void build_dir(DirHost &D, int n, int p, double L)
 
 // gamma and the reaction share of the implicit operator along dir
 // (eq. varPR_wildfire: tau/2 both directions; eq. varCN: tau/4 along x and
-// tau/2 along y; the linear reaction belongs to L1, the x operator).
+// tau/2 along y; the linear reaction belongs to L1, the x operator).  The
+// explicit scheme inverts the mass matrices only (gamma = 0).
 static void op_params(const iga_plan *pl, int dir, double &g, double &react)
 {
     if (pl->d.scheme == IGA_PR) g = 0.5 * pl->d.dt;
+    else if (pl->d.scheme == IGA_EXPLICIT) g = 0.0;
     else g = dir == 0 ? 0.25 * pl->d.dt : 0.5 * pl->d.dt;
     react = dir == 0 ? pl->d.c.c_react : 0.0;
 }

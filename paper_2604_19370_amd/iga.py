@@ -16,7 +16,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libiga.so")
 
 OK, EINVAL, ENOMEM, EDEVICE, ENONFINITE, EUNSUPPORTED, ESTATE = range(7)
-PR, STRANG_CN = 0, 1
+PR, STRANG_CN, EXPLICIT = 0, 1, 2
 FP64, FP32_REFINE = 0, 1
 WIND_CONST, WIND_SINCOS = 0, 1
 
@@ -128,7 +128,7 @@ def make_desc(nel_x, nel_y, p, len_x, len_y, dt, scheme, precision="fp64", wind=
     d = PlanDesc()
     d.nel_x, d.nel_y, d.p = int(nel_x), int(nel_y), int(p)
     d.len_x, d.len_y, d.dt = float(len_x), float(len_y), float(dt)
-    d.scheme = {"pr": PR, "strang": STRANG_CN}.get(scheme, scheme)
+    d.scheme = {"pr": PR, "strang": STRANG_CN, "explicit": EXPLICIT}.get(scheme, scheme)
     d.precision = {"fp64": FP64, "fp32": FP32_REFINE, "fp32_refine": FP32_REFINE}.get(precision,
                                                                                       precision)
     co = default_coeffs()

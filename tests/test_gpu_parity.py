@@ -3,7 +3,7 @@
 FP64 plans must match the oracle to 1e-12 relative L2 per step (the tolerance
 of the method's double-precision path); FP32-with-refinement plans to 1e-6
 per step.  Cases span several workgroup tiles with ragged tails, both degrees,
-both schemes, every line-solve schedule, the minimum mesh, and edge cases.
+all three schemes, every line-solve schedule, the minimum mesh, and edge cases.
 """
 import numpy as np
 import pytest
@@ -51,7 +51,17 @@ CASES = [
     (33, 27, 1, "pr"),     # linear B-splines (band 3)
     (90, 51, 1, "strang"),
     (3, 3, 1, "strang"),   # minimum mesh for p=1
+    # explicit L2-projection steps (all terms explicit, M (x) M solves)
+    (37, 29, 2, "explicit"),
+    (45, 33, 3, "explicit"),
+    (33, 27, 1, "explicit"),
+    (5, 5, 2, "explicit"),
 ]
+
+
+def substeps(scheme):
+    """Substeps with a quadrature right-hand side."""
+    return {"pr": (0, 1), "strang": (0, 2), "explicit": (0,)}[scheme]
 
 
 @pytest.mark.parametrize("nx,ny,p,scheme", CASES)
@@ -153,7 +163,7 @@ def test_assemble_fp64(nx, ny, p, scheme):
     sc = inputs.small_case(200 + nx, nx, ny, p, scheme)
     pl, od = plan_and_oracle(sc)
     T = sc.T0 + np.random.default_rng(3).uniform(0, 600, sc.T0.shape)
-    for substep in ((0, 1) if scheme == "pr" else (0, 2)):
+    for substep in substeps(scheme):
         Rref, RFref = oracle.assemble(od, substep, T, sc.fuel0, with_fuel=True)
         t, f = dev(T), dev(sc.fuel0)
         r, rf = torch.zeros_like(t), torch.zeros_like(t)
@@ -185,7 +195,7 @@ def test_assemble_fp32_increment_form(nx, ny, p, scheme):
     T = (sc.T0 + np.random.default_rng(4).uniform(0, 600, sc.T0.shape)).astype(np.float32)
     T = T.astype(np.float64)
     F = sc.fuel0.astype(np.float32).astype(np.float64)
-    for substep in ((0, 1) if scheme == "pr" else (0, 2)):
+    for substep in substeps(scheme):
         R, RF = oracle.assemble(od, substep, T, F, with_fuel=True)
         ax, mx = oracle.operator(od, 0, 0), oracle.operator(od, 0, 1)
         ay, my = oracle.operator(od, 1, 0), oracle.operator(od, 1, 1)
