@@ -49,6 +49,8 @@ def parse():
                          "(rows per lane) instead of autotuning")
     ap.add_argument("--no-ensembles", action="store_true",
                     help="skip the ensemble workloads (64 uneven members; 16 cubic 2048^2 members)")
+    ap.add_argument("--no-paper-meshes", action="store_true",
+                    help="skip the FP64 runs on the meshes of the paper's scalability study")
     return ap.parse_args()
 
 
@@ -259,6 +261,29 @@ def ensembles(torch, iga, inputs):
     return res
 
 
+# The meshes and step counts of the paper's CPU scalability study (Section 7):
+# 100^2 / 600^2 / 1500^2 elements, 120 / 720 / 1080 steps, p = 1, 2, 3.  The
+# paper does not state the scheme or the inputs of those runs; here they are
+# the regional Strang-CN inputs at that size, FP64 (the paper's precision),
+# graph-replayed.
+PAPER_MESHES = ((100, 120), (600, 720), (1500, 1080))
+
+
+def paper_meshes(torch, iga, inputs):
+    out = {}
+    for p in (1, 2, 3):
+        for nel, steps in PAPER_MESHES:
+            sc = inputs.regional_strang(seed=1, nel=nel, steps=steps, p=p)
+            pl = iga.Plan.from_scenario(sc, precision="fp64")
+            pl.factor()
+            wall, ev, T, F = time_steps(pl, sc, steps, 2, torch)
+            out[f"p{p}_{nel}x{nel}_{steps}steps"] = {
+                "dofs": sc.ndof, "seconds": round(wall, 5),
+                "value": round(sc.ndof * steps / wall, 1), "unit": "DOF-steps/s"}
+            pl.close()
+    return out
+
+
 def cpu_baseline(sc, budget_s):
     import oracle
     d = oracle.desc_from_scenario(sc)
@@ -360,6 +385,8 @@ def main():
     }
     if not args.no_ensembles:
         line["ensembles"] = ensembles(torch, iga, inputs)
+    if not args.no_paper_meshes:
+        line["paper_meshes_fp64"] = paper_meshes(torch, iga, inputs)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(sc, args.cpu_seconds)
     print(json.dumps(line), flush=True)
