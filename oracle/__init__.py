@@ -78,6 +78,8 @@ def lib() -> ctypes.CDLL:
         L.oracle_step_flagged.argtypes = [ctypes.POINTER(Desc), dp, dp, ctypes.c_double,
                                           ctypes.c_double, ctypes.c_void_p]
         L.oracle_run.argtypes = [ctypes.POINTER(Desc), dp, dp, ctypes.c_int]
+        L.oracle_step_forced.argtypes = [ctypes.POINTER(Desc), dp, dp, dp, dp]
+        L.oracle_quad_points.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, dp]
         L.oracle_eval_grid.argtypes = [ctypes.POINTER(Desc), dp, dp, ctypes.c_int, dp,
                                        ctypes.c_int, dp]
         L.oracle_burned_fraction.argtypes = [ctypes.POINTER(Desc), dp, ctypes.c_double]
@@ -194,6 +196,30 @@ def step(desc: Desc, T: np.ndarray, fuel: np.ndarray):
     fuel = np.array(fuel, dtype=np.float64, order="C", copy=True)
     _check(lib().oracle_step(ctypes.byref(desc), _p(T), _p(fuel)), "step")
     return T, fuel
+
+
+def step_forced(desc: Desc, T: np.ndarray, fuel: np.ndarray, src0: np.ndarray, src1=None):
+    """One step with a source added to F, sampled at the quadrature points
+    (arrays of shape (nel_x*(p+1), nel_y*(p+1)); src1 None for the explicit
+    scheme)."""
+    T = np.array(T, dtype=np.float64, order="C", copy=True)
+    fuel = np.array(fuel, dtype=np.float64, order="C", copy=True)
+    s0 = np.ascontiguousarray(src0, dtype=np.float64)
+    s1 = None if src1 is None else np.ascontiguousarray(src1, dtype=np.float64)
+    q = desc.p + 1
+    for a in (s0, s1):
+        if a is not None and a.shape != (desc.nel_x * q, desc.nel_y * q):
+            raise ValueError(f"source shape {a.shape}")
+    _check(lib().oracle_step_forced(ctypes.byref(desc), _p(T), _p(fuel), _p(s0),
+                                    None if s1 is None else _p(s1)), "step_forced")
+    return T, fuel
+
+
+def quad_points(n: int, p: int, L: float) -> np.ndarray:
+    """Gauss points of the n elements of [0, L], element by element."""
+    x = np.zeros(n * (p + 1))
+    _check(lib().oracle_quad_points(n, p, L, _p(x)), "quad_points")
+    return x
 
 
 def step_flagged(desc: Desc, T: np.ndarray, fuel: np.ndarray, dT: float, dF: float):

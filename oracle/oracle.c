@@ -404,6 +404,9 @@ static void wind_at(const oracle_desc *d, double x, double y, double *bx, double
  * the explicit scheme,
  *   f = -C_adv (b - bbar).grad S + C_forcing - C_rad S^4
  *       + [S > T_ig and fuel > thr] C_ign S exp(-T_act / S)
+ * plus, when src is given, a source s sampled at the quadrature points (the
+ * forcing f of eq. (linear) / eq. (nonlinear) in the manufactured-solution
+ * study of Section 6.1), src[(ex*nq + qx) * (nel_y*nq) + ey*nq + qy];
  * and, when rhs_fuel is given, the fuel right-hand side of the compute_rhs
  * listing,  fuel v - tau * rate * [ign] S exp(-T_act/S) fuel v. */
 /* Elements whose ignition decision is within (dT, dF) of its thresholds at
@@ -416,7 +419,8 @@ typedef struct {
 
 static int assemble_quadrature(const oracle_desc *d, double ax, double ay,
                                double beta, const double *T, const double *fuel,
-                               double *rhs_T, double *rhs_fuel, const ambiguity *amb)
+                               const double *src, double *rhs_T, double *rhs_fuel,
+                               const ambiguity *amb)
 {
     int p = d->p, nq = p + 1;
     int Ny = d->nel_y + p, Nx = d->nel_x + p;
@@ -459,6 +463,7 @@ static int assemble_quadrature(const oracle_desc *d, double ax, double ay,
                         double S2 = S * S;
                         double f = -c->c_adv * ((bxv - d->bbar_x) * Sx + (byv - d->bbar_y) * Sy)
                                    + c->c_forcing - c->c_rad * S2 * S2 + c->c_ign * arr;
+                        if (src) f += src[eqx * ((size_t)d->nel_y * nq) + eqy];
                         double g = c->c_nld * S2 * S;
                         for (int a = 0; a <= p; ++a)
                             for (int b = 0; b <= p; ++b) {
@@ -539,18 +544,18 @@ int oracle_assemble(const oracle_desc *d, int substep, const double *T,
     }
     double ax, ay, beta;
     if (substep_params(d, substep, &ax, &ay, &beta)) return 1;
-    return assemble_quadrature(d, ax, ay, beta, T, fuel, rhs_T, rhs_fuel, NULL);
+    return assemble_quadrature(d, ax, ay, beta, T, fuel, NULL, rhs_T, rhs_fuel, NULL);
 }
 
 static int assemble_checked(const oracle_desc *d, int substep, const double *T,
-                            const double *fuel, double *rhs_T, double *rhs_fuel,
-                            const ambiguity *amb)
+                            const double *fuel, const double *src, double *rhs_T,
+                            double *rhs_fuel, const ambiguity *amb)
 {
-    if (!amb || (d->scheme == ORACLE_STRANG && substep == 1))
+    if ((!amb && !src) || (d->scheme == ORACLE_STRANG && substep == 1))
         return oracle_assemble(d, substep, T, fuel, rhs_T, rhs_fuel);
     double ax, ay, beta;
     if (substep_params(d, substep, &ax, &ay, &beta)) return 1;
-    return assemble_quadrature(d, ax, ay, beta, T, fuel, rhs_T, rhs_fuel, amb);
+    return assemble_quadrature(d, ax, ay, beta, T, fuel, src, rhs_T, rhs_fuel, amb);
 }
 
 /* (A (x) B) X = R: solve A along the x-lines, then B along the y-lines. */
@@ -561,7 +566,9 @@ static int kron_solve(const oracle_desc *d, int which_x, int which_y, double *X)
     return rc;
 }
 
-static int step_impl(const oracle_desc *d, double *T, double *fuel, const ambiguity *amb)
+/* src0 / src1: sources of the first / second quadrature substep (or NULL) */
+static int step_impl(const oracle_desc *d, double *T, double *fuel, const ambiguity *amb,
+                     const double *src0, const double *src1)
 {
     if (!valid_desc(d) || !T || !fuel) return 1;
     size_t n = (size_t)(d->nel_x + d->p) * (d->nel_y + d->p);
@@ -571,24 +578,24 @@ static int step_impl(const oracle_desc *d, double *T, double *fuel, const ambigu
     int rc;
     if (d->scheme == ORACLE_PR) {
         /* eq. (matrixPR): [A^x (x) M^y] T^{n+1/2} = ..., [M^x (x) A^y] T^{n+1} = ... */
-        rc = assemble_checked(d, 0, T, fuel, R, RF, amb);
+        rc = assemble_checked(d, 0, T, fuel, src0, R, RF, amb);
         if (!rc) rc = kron_solve(d, 0, 1, R);
         if (!rc) memcpy(T, R, sizeof(double) * n);
-        if (!rc) rc = assemble_checked(d, 1, T, fuel, R, NULL, amb);
+        if (!rc) rc = assemble_checked(d, 1, T, fuel, src1, R, NULL, amb);
         if (!rc) rc = kron_solve(d, 1, 0, R);
         if (!rc) memcpy(T, R, sizeof(double) * n);
     } else if (d->scheme == ORACLE_EXPLICIT) {
         /* (Mx (x) My) T^{n+1} = R(T^n, fuel^n) */
-        rc = assemble_checked(d, 0, T, fuel, R, RF, amb);
+        rc = assemble_checked(d, 0, T, fuel, src0, R, RF, amb);
         if (!rc) rc = kron_solve(d, 1, 1, R);
         if (!rc) memcpy(T, R, sizeof(double) * n);
     } else {
         /* eq. (matrixCN): T^n -> T* -> T** -> T^{n+1} */
-        rc = assemble_checked(d, 0, T, fuel, R, RF, amb);
+        rc = assemble_checked(d, 0, T, fuel, src0, R, RF, amb);
         if (!rc) rc = kron_solve(d, 0, 1, R);
         if (!rc) rc = oracle_assemble(d, 1, R, fuel, T, NULL);
         if (!rc) rc = kron_solve(d, 1, 0, T);
-        if (!rc) rc = assemble_checked(d, 2, T, fuel, R, NULL, amb);
+        if (!rc) rc = assemble_checked(d, 2, T, fuel, src1, R, NULL, amb);
         if (!rc) rc = kron_solve(d, 0, 1, R);
         if (!rc) memcpy(T, R, sizeof(double) * n);
     }
@@ -602,7 +609,27 @@ static int step_impl(const oracle_desc *d, double *T, double *fuel, const ambigu
 
 int oracle_step(const oracle_desc *d, double *T, double *fuel)
 {
-    return step_impl(d, T, fuel, NULL);
+    return step_impl(d, T, fuel, NULL, NULL, NULL);
+}
+
+int oracle_step_forced(const oracle_desc *d, double *T, double *fuel, const double *src0,
+                       const double *src1)
+{
+    if (!src0 || (d && d->scheme == ORACLE_EXPLICIT && src1) ||
+        (d && d->scheme != ORACLE_EXPLICIT && !src1))
+        return 1;
+    return step_impl(d, T, fuel, NULL, src0, src1);
+}
+
+int oracle_quad_points(int n, int p, double L, double *xq)
+{
+    if (!xq || n < 1 || p < 1 || p > 3 || !(L > 0)) return 1;
+    dir1d D;
+    int rc = dir_init(&D, n, p, L);
+    if (rc) return rc;
+    memcpy(xq, D.xq, sizeof(double) * (size_t)n * (p + 1));
+    dir_free(&D);
+    return 0;
 }
 
 int oracle_step_flagged(const oracle_desc *d, double *T, double *fuel, double dT, double dF,
@@ -610,7 +637,7 @@ int oracle_step_flagged(const oracle_desc *d, double *T, double *fuel, double dT
 {
     if (!flags || !(dT >= 0) || !(dF >= 0)) return 1;
     ambiguity amb = {dT, dF, flags};
-    return step_impl(d, T, fuel, &amb);
+    return step_impl(d, T, fuel, &amb, NULL, NULL);
 }
 
 int oracle_run(const oracle_desc *d, double *T, double *fuel, int nsteps)

@@ -77,6 +77,17 @@ int oracle_assemble(const oracle_desc *d, int substep, const double *T,
                     const double *fuel, double *rhs_T, double *rhs_fuel);
 /* One full time step, in place. */
 int oracle_step(const oracle_desc *d, double *T, double *fuel);
+/* One step with a source s added to F (the forcing f of the manufactured-
+ * solution study, Section 6.1), sampled at the quadrature points:
+ * src[(ex*(p+1) + qx) * (nel_y*(p+1)) + ey*(p+1) + qy] at the points that
+ * oracle_quad_points lists.  src0 feeds the first quadrature substep (PR 0,
+ * Strang S1, explicit), src1 the second (PR 1, Strang S3; NULL for the
+ * explicit scheme, required otherwise). */
+int oracle_step_forced(const oracle_desc *d, double *T, double *fuel, const double *src0,
+                       const double *src1);
+/* Gauss points of the n elements of [0, L], element by element:
+ * xq[e*(p+1) + q], ascending. */
+int oracle_quad_points(int n, int p, double L, double *xq);
 /* oracle_step, and flags[ex * nel_y + ey] = 1 for every element with a
  * quadrature point, in any substep, where the ignition decision is within dT
  * of T_ig (with fuel above thr - dF) or within dF of the fuel threshold (with

@@ -264,3 +264,74 @@ def ring_of_fire(nel: int = 100, p: int = 2, scheme: str = "strang", dt: float =
     sc.fuel0 = np.ones((sc.Nx, sc.Ny))
     sc.T0 = np.ascontiguousarray(T_AMBIENT + t_comb * bump, dtype=np.float64)
     return sc
+
+
+# ---------------------------------------------------------------------------
+# manufactured solution (Section 6.1, stability and order study)
+# ---------------------------------------------------------------------------
+MMS_AMPS = ((80.0, 3.0), (30.0, 5.0), (110.0, 1.5))   # (amplitude, lambda) of the three terms
+
+
+@dataclasses.dataclass
+class Manufactured:
+    """u(x, y, t) = 300 + sum_k A_k (1 - cos 2 pi x/L)(1 - cos 2 pi y/L) e^{-lambda_k t}
+    on [0, L]^2 with L = 100, the exact solution of the paper's order study
+    (the mode indices the paper attaches to each term do not enter its
+    formula, so all three terms share one spatial shape).  Its normal
+    derivative vanishes on the boundary, matching the natural (zero-flux)
+    condition of the weak form.  `source` is the forcing f that makes u solve
+
+      u_t = -c_adv b.grad u + c_diff lap u + c_react u + div(c_nld u^3 grad u)
+            + c_forcing - c_rad u^4 + f
+
+    -- the generic equation with every smooth term; the fuel is zero, so the
+    ignition term is off.  The coefficients and the constant wind b are the
+    ones the stepper is given."""
+    coeffs: dict
+    bx: float = 0.0
+    by: float = 0.0
+    length: float = 100.0
+
+    def _parts(self, x, y, t):
+        a = 2.0 * np.pi / self.length
+        x, y = np.asarray(x, dtype=np.float64), np.asarray(y, dtype=np.float64)
+        cx, cy, sx, sy = np.cos(a * x), np.cos(a * y), np.sin(a * x), np.sin(a * y)
+        g = sum(A * np.exp(-lam * t) for A, lam in MMS_AMPS)
+        dg = sum(-lam * A * np.exp(-lam * t) for A, lam in MMS_AMPS)
+        phi = (1.0 - cx) * (1.0 - cy)
+        phx = a * sx * (1.0 - cy)
+        phy = a * (1.0 - cx) * sy
+        lap = a * a * (cx * (1.0 - cy) + (1.0 - cx) * cy)
+        return g, dg, phi, phx, phy, lap
+
+    def exact(self, x, y, t):
+        g, _, phi, _, _, _ = self._parts(x, y, t)
+        return T_AMBIENT + g * phi
+
+    def source(self, x, y, t):
+        c = self.coeffs
+        g, dg, phi, phx, phy, lap = self._parts(x, y, t)
+        u = T_AMBIENT + g * phi
+        ux, uy, ulap = g * phx, g * phy, g * lap
+        div_nld = c["c_nld"] * (3.0 * u * u * (ux * ux + uy * uy) + u ** 3 * ulap)
+        return (dg * phi + c["c_adv"] * (self.bx * ux + self.by * uy) - c["c_diff"] * ulap
+                - c["c_react"] * u - div_nld - c["c_forcing"] + c["c_rad"] * u ** 4)
+
+
+def manufactured(coeffs: dict, nel: int = 50, p: int = 2, scheme: str = "pr", dt: float = 1.0 / 16,
+                 t_end: float = 1.0, bx: float = 0.0, by: float = 0.0):
+    """Scenario of the order study on [0, 100]^2 with nel^2 elements: the
+    initial state is u(., ., 0) at the Greville points, the fuel zero, the
+    wind the constant (bx, by) (the paper does not state one; zero by
+    default).  Returns (scenario, Manufactured)."""
+    mms = Manufactured(coeffs=dict(coeffs), bx=bx, by=by)
+    L = mms.length
+    g = greville(nel, p) * L
+    steps = int(round(t_end / dt))
+    sc = Scenario(name=f"manufactured_{nel}_p{p}_{scheme}_dt{dt:g}", nel_x=nel, nel_y=nel, p=p,
+                  len_x=L, len_y=L, dt=dt, scheme=scheme, steps=steps,
+                  wind=Wind("const", bx, by), seed=0, ignitions=[])
+    sc.fuel_raster = np.zeros((nel, nel))
+    sc.fuel0 = np.zeros((sc.Nx, sc.Ny))
+    sc.T0 = np.ascontiguousarray(mms.exact(g[:, None], g[None, :], 0.0), dtype=np.float64)
+    return sc, mms
