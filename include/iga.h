@@ -172,6 +172,22 @@ iga_status iga_line_solve(const iga_plan *plan, int32_t dir, int32_t which, void
  * Requires iga_factor_1d. */
 iga_status iga_step(iga_plan *plan, void *T, void *fuel, void *stream);
 
+/* One step with a source term s(x, y) added to F (the forcing f of the
+ * manufactured-solution study of Section 6.1), sampled at the Gauss points
+ * that iga_plan_quadrature_points lists: src[(ex*Q + qx) * (nel_y*Q) + ey*Q
+ * + qy], Q = p + 1, point (x_{ex*Q+qx}, y_{ey*Q+qy}), in the plan's precision,
+ * device memory, 16-byte aligned, not aliasing the state.  src0 feeds the
+ * first quadrature substep (PR substep 0, Strang S1, explicit), src1 the
+ * second (PR substep 1, Strang S3; must be NULL for explicit plans, non-NULL
+ * otherwise); the caller samples each at the time it stands for (for
+ * instance the start of the substep).  Errors as iga_step. */
+iga_status iga_step_forced(iga_plan *plan, void *T, void *fuel, const void *src0, const void *src1,
+                           void *stream);
+
+/* The Gauss points of direction dir (0 = x, 1 = y): nel*(p+1) coordinates,
+ * element by element, ascending, written to the host array x. */
+iga_status iga_plan_quadrature_points(const iga_plan *plan, int32_t dir, double *x);
+
 /* nsteps steps, in place, replayed from a HIP graph captured on first use for
  * this (T, fuel) pair.  With desc.check_every > 0 the state is tested for
  * NaN/Inf every check_every steps (this synchronises `stream`) and

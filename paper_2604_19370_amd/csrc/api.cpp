@@ -109,7 +109,9 @@ void step_phases(const iga_plan *pl, void *T, void *fuel, StepPhases &sp)
     }
 }
 
-static iga_status step_impl(iga_plan *pl, void *T, void *fuel, hipStream_t s)
+// src0 / src1: sources of the first / second quadrature substep (forced steps)
+static iga_status step_impl(iga_plan *pl, void *T, void *fuel, hipStream_t s,
+                            const void *src0 = nullptr, const void *src1 = nullptr)
 {
     StepPhases sp;
     step_phases(pl, T, fuel, sp);
@@ -117,10 +119,12 @@ static iga_status step_impl(iga_plan *pl, void *T, void *fuel, hipStream_t s)
     auto sweep = [&](int dir, const std::vector<SweepJob> &j) {
         return launch_sweep(pl, dir, j.data(), (int)j.size(), s);
     };
-    if ((st = launch_assemble(pl, sp.a1.substep, sp.a1.T, sp.a1.fuel, sp.a1.R, sp.a1.RF, s))) return st;
+    if ((st = launch_assemble(pl, sp.a1.substep, sp.a1.T, sp.a1.fuel, sp.a1.R, sp.a1.RF, s, src0)))
+        return st;
     if ((st = sweep(0, sp.x1)) || (st = sweep(1, sp.y1))) return st;
     if (!sp.two) return IGA_OK;
-    if ((st = launch_assemble(pl, sp.a2.substep, sp.a2.T, sp.a2.fuel, sp.a2.R, sp.a2.RF, s))) return st;
+    if ((st = launch_assemble(pl, sp.a2.substep, sp.a2.T, sp.a2.fuel, sp.a2.R, sp.a2.RF, s, src1)))
+        return st;
     if ((st = sweep(0, sp.x2)) || (st = sweep(1, sp.y2))) return st;
     return IGA_OK;
 }
@@ -273,6 +277,35 @@ iga_status iga_step(iga_plan *plan, void *T, void *fuel, void *stream)
     if (T == fuel) return fail(IGA_EINVAL, "T and fuel must be different buffers");
     if (!plan->factored) return fail(IGA_ESTATE, "iga_factor_1d has not been called");
     return step_impl(plan, T, fuel, static_cast<hipStream_t>(stream));
+}
+
+iga_status iga_step_forced(iga_plan *plan, void *T, void *fuel, const void *src0, const void *src1,
+                           void *stream)
+{
+    if (!plan) return fail(IGA_EINVAL, "plan is NULL");
+    iga_status st;
+    if ((st = check_field(T, "T")) || (st = check_field(fuel, "fuel")) ||
+        (st = check_field(src0, "src0")))
+        return st;
+    if (plan->d.scheme == IGA_EXPLICIT) {
+        if (src1) return fail(IGA_EINVAL, "explicit plans take one source (src1 must be NULL)");
+    } else if ((st = check_field(src1, "src1"))) {
+        return st;
+    }
+    if (T == fuel) return fail(IGA_EINVAL, "T and fuel must be different buffers");
+    if (src0 == T || src0 == fuel || (src1 && (src1 == T || src1 == fuel)))
+        return fail(IGA_EINVAL, "sources must not alias the state");
+    if (!plan->factored) return fail(IGA_ESTATE, "iga_factor_1d has not been called");
+    return step_impl(plan, T, fuel, static_cast<hipStream_t>(stream), src0, src1);
+}
+
+iga_status iga_plan_quadrature_points(const iga_plan *plan, int32_t dir, double *x)
+{
+    if (!plan || !x) return fail(IGA_EINVAL, "NULL argument");
+    if (dir != 0 && dir != 1) return fail(IGA_EINVAL, "dir must be 0 or 1");
+    const std::vector<double> &q = dir ? plan->Y.xq : plan->X.xq;
+    std::memcpy(x, q.data(), q.size() * sizeof(double));
+    return IGA_OK;
 }
 
 iga_status iga_run(iga_plan *plan, void *T, void *fuel, int64_t nsteps, void *stream)

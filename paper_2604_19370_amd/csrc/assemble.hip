@@ -10,6 +10,9 @@
 //       + [S > T_ig and fuel > thr] C_ign S exp(-T_act/S)
 // and, for the first substep of a step, the fuel right-hand side of the
 // compute_rhs listing (Section 7): fuel v (1 - tau rate [ign] S exp(-T_act/S)).
+// A forced step adds to f a source sampled at the quadrature points (the
+// forcing of the manufactured-solution study, Section 6.1); that is a
+// separate compile-time variant, the unforced kernels do not test for it.
 // FP32 plans assemble the same quantities in increment form, R - A_impl S
 // (A_impl the substep's implicit Kronecker operator), so that the float
 // right-hand side carries only the O(tau) change of the state.
@@ -56,6 +59,10 @@ template <typename T> struct AsmParams {
     T t_ig, t_skip, fthr, t_act;
     int fuel_all;       // fuel right-hand side nonzero without ignition (direct form)
     int nel_x, nel_y, Nx, Ny, rows, nstrips, ntiles;
+    // source samples src[(ex*Q + qx) * nel_y*Q + ey*Q + qy] (forced variant),
+    // weighted by src_w[qx] = beta * x weight
+    const T *src;
+    T src_w[4];
 };
 
 template <int N> struct Ic {
@@ -63,7 +70,7 @@ template <int N> struct Ic {
 };
 
 // The work of wavefront gw (strip gw mod nstrips, tile gw / nstrips).
-template <typename T, int P, bool FUEL>
+template <typename T, int P, bool FUEL, bool SRC = false>
 __device__ __forceinline__ void assemble_body(const AsmParams<T> &a, const int gw)
 {
     constexpr int Q = P + 1;
@@ -208,6 +215,11 @@ __device__ __forceinline__ void assemble_body(const AsmParams<T> &a, const int g
                     a0 += a.rad_w[qx] * (S2 * S2);
                     a0 += a.cs_w[qx] * S;
                     a0 += kxw[qx][qy] * Sx;
+                    if constexpr (SRC) {
+                        if (eyok)
+                            a0 += a.src_w[qx] * a.src[((size_t)ex * Q + qx) * ((size_t)a.nel_y * Q) +
+                                                     (size_t)ey * Q + qy];
+                    }
                     const T ax = (g + a.dx_w[qx]) * Sx;
                     const T ay = (g + a.dy_w[qx]) * Sy;
 #pragma unroll
@@ -313,12 +325,12 @@ __device__ __forceinline__ void assemble_body(const AsmParams<T> &a, const int g
     }
 }
 
-template <typename T, int P, bool FUEL>
+template <typename T, int P, bool FUEL, bool SRC>
 __global__ __launch_bounds__(256) void k_assemble(AsmParams<T> a)
 {
     const int gw = blockIdx.x * (blockDim.x >> 6) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     if (gw >= a.nstrips * a.ntiles) return;
-    assemble_body<T, P, FUEL>(a, gw);
+    assemble_body<T, P, FUEL, SRC>(a, gw);
 }
 
 // Batched launch over the members of an ensemble: wavefront w does wavefront
@@ -335,7 +347,7 @@ __global__ __launch_bounds__(256) void k_assemble_batch(const AsmParams<T> *__re
 
 template <typename T>
 static void make_params(const iga_plan *pl, int substep, const void *S, const void *F, void *R,
-                        void *RF, AsmParams<T> &a)
+                        void *RF, AsmParams<T> &a, const void *src = nullptr)
 {
     const iga_plan_desc &d = pl->d;
     const int P = pl->P, Q = P + 1;
@@ -394,7 +406,9 @@ static void make_params(const iga_plan *pl, int substep, const void *S, const vo
         a.ign_w[q] = (T)(beta * d.c.c_ign * w);
         a.cf_w[q] = (T)(cf * w);
         a.rate_w[q] = (T)(d.dt * d.c.fuel_rate * w);
+        a.src_w[q] = (T)(beta * w);
     }
+    a.src = static_cast<const T *>(src);
     a.cx = (T)(kx * d.c.c_adv * d.wind.bbar_x);
     a.cy = (T)(ky * d.c.c_adv * d.wind.bbar_y);
     a.bca = (T)(beta * d.c.c_adv);
@@ -416,16 +430,21 @@ static void make_params(const iga_plan *pl, int substep, const void *S, const vo
 
 template <typename T>
 static iga_status launch_t(const iga_plan *pl, int substep, const void *S, const void *F, void *R,
-                           void *RF, hipStream_t s)
+                           void *RF, const void *src, hipStream_t s)
 {
     AsmParams<T> a;
-    make_params<T>(pl, substep, S, F, R, RF, a);
+    make_params<T>(pl, substep, S, F, R, RF, a, src);
     const int P = pl->P;
     const int waves = a.nstrips * a.ntiles;
     const int blocks = (waves + 3) / 4;
     const bool fuel = RF != nullptr;
-#define IGA_ASM(P_, FU_) \
-    hipLaunchKernelGGL((k_assemble<T, P_, FU_>), dim3(blocks), dim3(256), 0, s, a)
+#define IGA_ASM(P_, FU_)                                                                          \
+    do {                                                                                          \
+        if (src)                                                                                  \
+            hipLaunchKernelGGL((k_assemble<T, P_, FU_, true>), dim3(blocks), dim3(256), 0, s, a); \
+        else                                                                                      \
+            hipLaunchKernelGGL((k_assemble<T, P_, FU_, false>), dim3(blocks), dim3(256), 0, s, a); \
+    } while (0)
     if (P == 1) {
         if (fuel) IGA_ASM(1, true);
         else IGA_ASM(1, false);
@@ -444,10 +463,10 @@ static iga_status launch_t(const iga_plan *pl, int substep, const void *S, const
 }
 
 iga_status launch_assemble(const iga_plan *pl, int substep, const void *S, const void *F, void *R,
-                           void *RF, hipStream_t s)
+                           void *RF, hipStream_t s, const void *src)
 {
-    return pl->fp32 ? launch_t<float>(pl, substep, S, F, R, RF, s)
-                    : launch_t<double>(pl, substep, S, F, R, RF, s);
+    return pl->fp32 ? launch_t<float>(pl, substep, S, F, R, RF, src, s)
+                    : launch_t<double>(pl, substep, S, F, R, RF, src, s);
 }
 
 template <typename T>

@@ -199,8 +199,9 @@ iga_status choose_window_schedule(iga_plan *pl, int dir, int lines, int mm);
 iga_status launch_factor(iga_plan *pl, hipStream_t s);
 
 // kernels (assemble.hip)
+// src: optional source sampled at the quadrature points (forced steps)
 iga_status launch_assemble(const iga_plan *pl, int substep, const void *T, const void *fuel,
-                           void *rhs, void *rhs_fuel, hipStream_t s);
+                           void *rhs, void *rhs_fuel, hipStream_t s, const void *src = nullptr);
 
 // kernels (sweep.hip)
 struct SweepJob {
@@ -236,6 +237,7 @@ struct AsmArgs {
     int substep;
     const void *T, *fuel;
     void *R, *RF;
+    const void *src = nullptr;   // forced steps only (never batched)
 };
 iga_status build_assemble_batch(const std::vector<iga_plan *> &pls, const std::vector<AsmArgs> &args,
                                 BatchLaunch &out);

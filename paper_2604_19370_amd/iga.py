@@ -27,8 +27,8 @@ EXPORTED = ("iga_default_coeffs", "iga_plan_create", "iga_plan_destroy", "iga_pl
             "iga_plan_solver", "iga_ensemble_create", "iga_ensemble_destroy",
             "iga_ensemble_size", "iga_ensemble_launches", "iga_ensemble_step", "iga_ensemble_run",
             "iga_ensemble_set_schedule", "iga_ensemble_set_window_schedule",
-            "iga_ensemble_set_assembly_rows", "iga_ensemble_autotune",
-            "iga_last_error")
+            "iga_ensemble_set_assembly_rows", "iga_ensemble_autotune", "iga_step_forced",
+            "iga_plan_quadrature_points", "iga_last_error")
 
 _COEFF_NAMES = ("c_adv", "c_diff", "c_react", "c_nld", "c_ign", "t_ig", "fuel_thr", "t_act",
                 "c_forcing", "c_rad", "fuel_rate")
@@ -67,6 +67,12 @@ def lib() -> ctypes.CDLL:
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"{LIB_PATH} is missing: build it with "
                                "`python -m paper_2604_19370_amd.build`")
+        # torch ships its own HIP runtime under the same soname as the system
+        # one libiga.so is linked against.  Loaded after torch's, libiga.so
+        # binds to it; loaded first, it would pull in the system copy and
+        # torch would then load a second runtime that finds no GPU.  So torch
+        # (which owns the device memory and streams passed in) loads first.
+        import torch  # noqa: F401
         L = ctypes.CDLL(LIB_PATH)
         vp, i32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
         L.iga_default_coeffs.argtypes = [ctypes.POINTER(Coeffs)]
@@ -99,6 +105,8 @@ def lib() -> ctypes.CDLL:
         L.iga_ensemble_set_schedule.argtypes = [vp, i32, i32, i32]
         L.iga_ensemble_set_assembly_rows.argtypes = [vp, i32]
         L.iga_ensemble_autotune.argtypes = [vp, pp, pp, i32, vp]
+        L.iga_step_forced.argtypes = [vp, vp, vp, vp, vp, vp]
+        L.iga_plan_quadrature_points.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_double)]
         L.iga_last_error.argtypes = []
         L.iga_last_error.restype = ctypes.c_char_p
         for name in EXPORTED[1:-1]:
@@ -227,6 +235,34 @@ class Plan:
     def run(self, T, fuel, nsteps, stream=None):
         _check(lib().iga_run(self._h, self._field(T, "T"), self._field(fuel, "fuel"),
                              int(nsteps), _stream(stream)), "iga_run")
+
+    def quadrature_points(self, dir):
+        """Gauss points of direction dir, element by element (numpy float64)."""
+        import numpy as np
+        n = (self.desc.nel_y if dir else self.desc.nel_x) * (self.desc.p + 1)
+        x = np.zeros(n)
+        _check(lib().iga_plan_quadrature_points(
+            self._h, int(dir), x.ctypes.data_as(ctypes.POINTER(ctypes.c_double))),
+            "iga_plan_quadrature_points")
+        return x
+
+    def _source(self, t, name):
+        q = self.desc.p + 1
+        shape = (self.desc.nel_x * q, self.desc.nel_y * q)
+        if t.dtype != self.dtype or not t.is_contiguous() or tuple(t.shape) != shape:
+            raise ValueError(f"{name}: expected contiguous {self.dtype} tensor of shape {shape}, "
+                             f"got {t.dtype} {tuple(t.shape)}")
+        if t.device.type != "cuda":
+            raise ValueError(f"{name} must be on the GPU")
+        return _ptr(t)
+
+    def step_forced(self, T, fuel, src0, src1=None, stream=None):
+        """One step with sources sampled at the quadrature points added to F
+        (src1 None for the explicit scheme)."""
+        _check(lib().iga_step_forced(self._h, self._field(T, "T"), self._field(fuel, "fuel"),
+                                     self._source(src0, "src0"),
+                                     None if src1 is None else self._source(src1, "src1"),
+                                     _stream(stream)), "iga_step_forced")
 
     def schedule(self, dir):
         v = [ctypes.c_int32() for _ in range(4)]

@@ -84,3 +84,17 @@ def test_ensemble_arguments_are_checked_before_any_device_work():
     n = ctypes.c_int32()
     assert L.iga_ensemble_size(None, ctypes.byref(n)) == iga.EINVAL
     assert L.iga_ensemble_launches(None, ctypes.byref(n)) == iga.EINVAL
+
+
+def test_one_hip_runtime_whatever_loads_first():
+    """Loading the library before anything imports torch must not leave two
+    HIP runtimes in the process (the second would find no GPU)."""
+    import subprocess
+    import sys
+    code = ("from paper_2604_19370_amd import iga; iga.default_coeffs(); import torch; "
+            "m = open('/proc/self/maps').read(); "
+            "print(len({l.split()[-1] for l in m.splitlines() if 'libamdhip64' in l}))")
+    out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=300,
+                         cwd=os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+    assert out.returncode == 0, out.stderr
+    assert out.stdout.strip().splitlines()[-1] == "1"
