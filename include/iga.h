@@ -215,18 +215,31 @@ iga_status iga_plan_set_schedule(iga_plan *plan, int32_t dir, int32_t lines,
  * wherever the operators allow them).  Each lane restarts forward and backward
  * substitution from a zero state `warmup` rows outside its chunk of
  * rows_per_lane rows; the plan chooses warmup from the factors so that the
- * restart changes the result by less than 2^-30 (FP32 plans, before the FP64
- * refinement) or 2^-55 (FP64 plans) relative to the state, and refuses
- * (IGA_EUNSUPPORTED) operators that would need more than 96 rows.
+ * restart changes the result by less than 2^-55 relative to the state (FP64
+ * plans) or, for FP32 plans, 2^-20 in the first solve and 2^-12 in the
+ * correction solve of the FP64-residual refinement (which also corrects the
+ * first solve's truncation), and refuses (IGA_EUNSUPPORTED) operators that
+ * would need more than 96 rows.
  * rows_per_lane in {9, 13, 17, 25, 33} (0: 17); lines in {1, 2, 4, 8, 16}.
  * Must follow iga_factor_1d; on failure the previous schedule is kept. */
 iga_status iga_plan_set_window_schedule(iga_plan *plan, int32_t dir, int32_t lines,
                                         int32_t rows_per_lane);
 
-/* Solver of direction dir: *windowed = 1 for windowed solves, 0 for the exact
- * chunk scan of iga_plan_set_schedule; *warmup = the windowed warm-up rows
- * (0 if windowed solves are not possible or before factorisation).  Either
- * pointer may be NULL. */
+/* Column waves for the x-lines of an FP32 plan: one line per lane, 64
+ * adjacent lines per wavefront, each wavefront a chunk of rows_per_chunk rows
+ * (16 or 32; 0: 32) with its own warm-up rows on both sides, so every access
+ * is a coalesced row and lanes never exchange data.  The x sweeps of a step
+ * then write into a second pair of scratch fields.  Under this schedule
+ * iga_line_solve(0, which) goes through a scratch field (which 0, 1) and
+ * refuses which 2 (IGA_EUNSUPPORTED).  IGA_EUNSUPPORTED for FP64 plans or x
+ * operators that decay too slowly for the kernel's compiled warm-ups.  Must
+ * follow iga_factor_1d; on failure the previous schedule is kept. */
+iga_status iga_plan_set_column_schedule(iga_plan *plan, int32_t rows_per_chunk);
+
+/* Solver of direction dir: *windowed = 2 for column waves, 1 for windowed
+ * solves, 0 for the exact chunk scan of iga_plan_set_schedule; *warmup = the
+ * windowed warm-up rows (0 if windowed solves are not possible or before
+ * factorisation).  Either pointer may be NULL. */
 iga_status iga_plan_solver(const iga_plan *plan, int32_t dir, int32_t *windowed, int32_t *warmup);
 
 /* Assembly schedule: element rows marched per wavefront (>= 1). */
@@ -236,7 +249,8 @@ int32_t iga_plan_assembly_rows(const iga_plan *plan);
 /* Autotuner: times, with HIP events on `stream`, the assembly of the first
  * substep for several element-row tiles and the line solves of each direction
  * for every windowed and exact schedule that fits, on the plan's scratch
- * buffers (T and fuel are only read), and keeps the fastest of each.  Synchronises `stream`; must
+ * buffers (T and fuel are only read), and keeps the fastest of each (column
+ * waves included for the x-lines of FP32 plans).  Synchronises `stream`; must
  * follow iga_factor_1d.  reps >= 1 launches per candidate. */
 iga_status iga_autotune(iga_plan *plan, const void *T, const void *fuel, int32_t reps,
                         void *stream);

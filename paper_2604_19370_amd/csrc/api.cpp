@@ -72,9 +72,13 @@ iga_status check_field(const void *p, const char *name)
 // R - (implicit operator) S, the solves give the increment, and the y sweep
 // adds the state it was taken from.  A PR or Strang step is six launches:
 // assembly, x sweep, y sweep, twice; an explicit step is the first three.
+// The x sweeps solve in place, or into second scratch fields under a
+// column-wave x schedule (whose waves read rows around their own chunk).
 void step_phases(const iga_plan *pl, void *T, void *fuel, StepPhases &sp)
 {
     void *R = pl->scratch_r.ptr, *RF = pl->scratch_rf.ptr;
+    const bool col = pl->sched[0].col != 0;
+    void *XR = col ? pl->scratch_r2.ptr : R, *XRF = col ? pl->scratch_rf2.ptr : RF;
     const void *bT = pl->delta ? T : nullptr, *bF = pl->delta ? fuel : nullptr;
     const int add = pl->delta ? 1 : 0;
     const bool pr = pl->d.scheme == IGA_PR;
@@ -83,29 +87,29 @@ void step_phases(const iga_plan *pl, void *T, void *fuel, StepPhases &sp)
     // region, and so do the windowed solves of it; those line blocks are skipped
     const int zs = pl->delta ? 1 : 0;
     sp.a1 = AsmArgs{0, T, fuel, R, RF};
-    sp.x1 = {{R, R, OP_AX, -1, -1, nullptr, 0}, {RF, RF, OP_MX, -1, -1, nullptr, 0, zs}};
+    sp.x1 = {{R, XR, OP_AX, -1, -1, nullptr, 0}, {RF, XRF, OP_MX, -1, -1, nullptr, 0, zs}};
     sp.two = true;
     if (pl->d.scheme == IGA_EXPLICIT) {
         // (M^x (x) M^y) solves of both right-hand sides, in the same launches
         sp.x1[0].op0 = OP_MX;
-        sp.y1 = {{R, T, OP_MY, -1, -1, bT, 0}, {RF, fuel, OP_MY, -1, -1, bF, 0, zs}};
+        sp.y1 = {{XR, T, OP_MY, -1, -1, bT, 0}, {XRF, fuel, OP_MY, -1, -1, bF, 0, zs}};
         sp.two = false;
         sp.x2.clear();
         sp.y2.clear();
     } else if (pr) {
-        sp.y1 = {{R, T, OP_MY, -1, -1, bT, 0}};
+        sp.y1 = {{XR, T, OP_MY, -1, -1, bT, 0}};
         // substep 2: y implicit
         sp.a2 = AsmArgs{1, T, fuel, R, nullptr};
-        sp.x2 = {{R, R, OP_MX, -1, -1, nullptr, 0}};
-        sp.y2 = {{R, T, OP_AY, -1, -1, bT, 0}, {RF, fuel, OP_MY, -1, -1, bF, 0, zs}};
+        sp.x2 = {{R, XR, OP_MX, -1, -1, nullptr, 0}};
+        sp.y2 = {{XR, T, OP_AY, -1, -1, bT, 0}, {XRF, fuel, OP_MY, -1, -1, bF, 0, zs}};
     } else {
         // S1's y solve fused with S2: T** = (A^y)^{-1} B^y T* along y, with
         // T* = (M^y)^{-1} R (+ T^n in increment form)
-        sp.y1 = {{R, T, OP_MY, BAND_BY, OP_AY, bT, add}};
+        sp.y1 = {{XR, T, OP_MY, BAND_BY, OP_AY, bT, add}};
         // S3
         sp.a2 = AsmArgs{2, T, fuel, R, nullptr};
-        sp.x2 = {{R, R, OP_AX, -1, -1, nullptr, 0}};
-        sp.y2 = {{R, T, OP_MY, -1, -1, bT, 0}, {RF, fuel, OP_MY, -1, -1, bF, 0, zs}};
+        sp.x2 = {{R, XR, OP_AX, -1, -1, nullptr, 0}};
+        sp.y2 = {{XR, T, OP_MY, -1, -1, bT, 0}, {XRF, fuel, OP_MY, -1, -1, bF, 0, zs}};
     }
 }
 
@@ -263,10 +267,21 @@ iga_status iga_line_solve(const iga_plan *plan, int32_t dir, int32_t which, void
     if (!plan->factored) return fail(IGA_ESTATE, "iga_factor_1d has not been called");
     const int A = dir ? OP_AY : OP_AX, M = dir ? OP_MY : OP_MX;
     const int B = dir ? BAND_BY : BAND_BX;
+    hipStream_t s = static_cast<hipStream_t>(stream);
     SweepJob j{x, x, A, -1, -1, nullptr, 0};
     if (which == 1) j.op0 = M;
+    if (plan->sched[dir].col) {
+        // column waves solve out of place: through the plan's scratch field
+        if (which == 2)
+            return fail(IGA_EUNSUPPORTED, "x <- A^{-1} B x needs a windowed or exact x schedule");
+        j.dst = plan->scratch_r2.ptr;
+        if ((st = launch_sweep(plan, dir, &j, 1, s))) return st;
+        IGA_HIP(hipMemcpyAsync(x, plan->scratch_r2.ptr, plan->ndof * plan->wsize,
+                               hipMemcpyDeviceToDevice, s));
+        return IGA_OK;
+    }
     if (which == 2) j = SweepJob{x, x, -1, B, A, nullptr, plan->delta ? 1 : 0};
-    return launch_sweep(plan, dir, &j, 1, static_cast<hipStream_t>(stream));
+    return launch_sweep(plan, dir, &j, 1, s);
 }
 
 iga_status iga_step(iga_plan *plan, void *T, void *fuel, void *stream)
@@ -396,11 +411,21 @@ iga_status iga_plan_set_window_schedule(iga_plan *plan, int32_t dir, int32_t lin
     return IGA_OK;
 }
 
+iga_status iga_plan_set_column_schedule(iga_plan *plan, int32_t rows_per_chunk)
+{
+    if (!plan) return fail(IGA_EINVAL, "plan is NULL");
+    if (!plan->factored) return fail(IGA_ESTATE, "iga_factor_1d has not been called");
+    iga_status st = choose_column_schedule(plan, rows_per_chunk);
+    if (st) return st;
+    plan->graph.reset();
+    return IGA_OK;
+}
+
 iga_status iga_plan_solver(const iga_plan *plan, int32_t dir, int32_t *windowed, int32_t *warmup)
 {
     if (!plan) return fail(IGA_EINVAL, "plan is NULL");
     if (dir != 0 && dir != 1) return fail(IGA_EINVAL, "dir must be 0 or 1");
-    if (windowed) *windowed = plan->sched[dir].win;
+    if (windowed) *windowed = plan->sched[dir].col ? 2 : plan->sched[dir].win;
     if (warmup) *warmup = plan->factored ? warmup_rows(plan, dir) : 0;
     return IGA_OK;
 }
@@ -468,7 +493,11 @@ iga_status iga_autotune(iga_plan *plan, const void *T, const void *fuel, int32_t
                 best = plan->sched[dir];
             }
         };
-        // windowed solves (where the operators decay fast enough)
+        // column waves (x-lines, FP32), then windowed solves (where the
+        // operators decay fast enough)
+        if (dir == 0)
+            for (int mm : {16, 32})
+                if (choose_column_schedule(plan, mm) == IGA_OK) consider();
         for (int mm : {9, 13, 17, 25, 33})
             for (int w : {1, 2, 4, 8, 16})
                 if (choose_window_schedule(plan, dir, w, mm) == IGA_OK) consider();
@@ -483,7 +512,8 @@ iga_status iga_autotune(iga_plan *plan, const void *T, const void *fuel, int32_t
                 consider();
             }
         }
-        if (best.win) st = choose_window_schedule(plan, dir, best.lines, best.mm);
+        if (best.col) st = choose_column_schedule(plan, best.mm);
+        else if (best.win) st = choose_window_schedule(plan, dir, best.lines, best.mm);
         else st = choose_schedule(plan, dir, best.lines, best.wpl);
         if (st) return st;
     }

@@ -80,6 +80,7 @@ inline int op_dir(int op) { return (op == OP_AX || op == OP_MX) ? 0 : 1; }
 struct Schedule {
     int lines = 4, wpl = 1, mm = 17;
     int win = 0;   // 1: windowed solves (see WinGeom), 0: exact chunk scan
+    int col = 0;   // 1 (x-lines, FP32): column waves, mm rows per chunk (sweep_col.h)
 };
 
 // Windowed line solves (truncated partition): each lane restarts forward and
@@ -93,7 +94,8 @@ struct Schedule {
 // c*mm - H + j); refinement rows (A, double) and explicit bands hold windows
 // of mm rows (the lane's own rows), with their own offsets (a*).
 struct WinGeom {
-    int H = 0;
+    int H = 0;    // warm-up rows (and window margin) of a solve
+    int Hc = 0;   // warm-up rows of the refinement's correction solve (<= H)
     int nhead = 0, tail0 = 0, tail1 = 0;
     int off_head = 0, off_tail = 0, off_canon = 0, off_id = 0, nrows = 0;
     int aoff_head = 0, aoff_tail = 0, aoff_canon = 0, aoff_id = 0, anrows = 0;
@@ -109,7 +111,8 @@ struct WinGeom {
 //   tb[c*P*P]           backward transfer matrix of chunk c
 struct OpHost {
     int K0 = 0, NK = 0, nrows = 0;
-    int H = 0;   // warm-up rows of windowed solves (0: decay too slow)
+    int H = 0;    // warm-up rows of windowed solves (0: decay too slow)
+    int Hc = 0;   // warm-up rows of the FP32 refinement's correction solve
     std::vector<double> rows, a64, tf, tb;
     std::vector<double> wrows, wa64;   // windowed strip tables (WinGeom)
 };
@@ -177,6 +180,7 @@ struct iga_plan {
     iga::DevBuf asm_bx, asm_by;                // [e][2][P+1][P+1]  (val, der), state precision
     iga::DevBuf asm_wx, asm_wy;                // wind remainders at x-qps / y-qps
     iga::DevBuf scratch_r, scratch_rf;         // right-hand sides
+    iga::DevBuf scratch_r2, scratch_rf2;       // x-solved right-hand sides (column waves)
     iga::DevBuf flag;                          // non-finite detector
     bool factored = false;
     iga::GraphCache graph;
@@ -194,6 +198,7 @@ int warmup_rows(const iga_plan *pl, int dir);   // 0 if a windowed solve is not 
 WinGeom window_geometry(const iga_plan *pl, int dir, int mm, int wpl);
 iga_status build_window_tables(iga_plan *pl, int dir);
 iga_status choose_window_schedule(iga_plan *pl, int dir, int lines, int mm);
+iga_status choose_column_schedule(iga_plan *pl, int mm);
 
 // kernels (factor.hip)
 iga_status launch_factor(iga_plan *pl, hipStream_t s);
@@ -214,11 +219,16 @@ struct SweepJob {
     int add_after;    // 1: result = x + op1^{-1} band x; 0: result = op1^{-1} band x
     // 1: a workgroup whose input lines are all zero leaves them untouched (set
     // only for single solves whose result then equals dst's content: in place
-    // without base, or dst == base)
+    // without base, or dst == base); the out-of-place column-wave kernel
+    // writes the zeros instead of solving
     int zero_skip = 0;
 };
 iga_status launch_sweep(const iga_plan *pl, int dir, const SweepJob *jobs, int njobs,
                         hipStream_t s);
+// column-wave x-line solves (sweep_col.hip): out of place, single solves
+bool csweep_ok(const iga_plan *pl);
+bool csweep_rows_ok(int mm);
+iga_status launch_csweep(const iga_plan *pl, const SweepJob *jobs, int njobs, hipStream_t s);
 int sweep_capacity(int m);           // smallest compiled register capacity >= m (0: none)
 
 // A prepared batched launch over ensemble members: kernel, per-member

@@ -234,6 +234,11 @@ iga_status upload_plan(iga_plan *pl)
     if ((st = upload_state(pl, pl->asm_wy, wy))) return st;
     IGA_HIP(pl->scratch_r.alloc(pl->ndof * pl->wsize));
     IGA_HIP(pl->scratch_rf.alloc(pl->ndof * pl->wsize));
+    if (pl->fp32) {
+        // out-of-place x solves (column waves)
+        IGA_HIP(pl->scratch_r2.alloc(pl->ndof * pl->wsize));
+        IGA_HIP(pl->scratch_rf2.alloc(pl->ndof * pl->wsize));
+    }
     IGA_HIP(pl->flag.alloc(64));
     for (int op = 0; op < NOPS; ++op) {
         const int N = op_dir(op) ? pl->Ny : pl->Nx;
@@ -411,6 +416,15 @@ int warmup_rows(const iga_plan *pl, int dir)
     return (h + 3) & ~3;   // the kernels' warm-up loops step by 4 rows
 }
 
+// warm-up rows of the correction solve of FP32 refinement (<= warmup_rows)
+static int correction_warmup_rows(const iga_plan *pl, int dir)
+{
+    int h = 0;
+    for (int op = 0; op < NOPS; ++op)
+        if (op_dir(op) == dir) h = std::max(h, pl->op_host[op].Hc);
+    return std::min((h + 3) & ~3, warmup_rows(pl, dir));
+}
+
 // Geometry of the windowed tables of direction dir for rows-per-lane mm and
 // wpl wavefronts per line (H = 0 if windowed solves are not possible).
 WinGeom window_geometry(const iga_plan *pl, int dir, int mm, int wpl)
@@ -421,6 +435,7 @@ WinGeom window_geometry(const iga_plan *pl, int dir, int mm, int wpl)
     if (H <= 0) return g;
     const int lanes = 64 * wpl;
     g.H = H;
+    g.Hc = pl->fp32 ? correction_warmup_rows(pl, dir) : H;
     g.tail1 = std::min(lanes, (N + mm - 1) / mm);
     // rows that are canonical in every table of the direction
     int K0 = 0, NK = N;
@@ -583,7 +598,13 @@ iga_status build_solve_tables(iga_plan *pl)
         if ((st = upload_vec<double>(pl->op_a64c[op], o.a64))) return st;
         // windowed solves: below float resolution of the refined FP32 solve,
         // below double rounding otherwise
-        o.H = compute_warmup(o, N, P, pl->fp32 ? std::ldexp(1.0, -30) : std::ldexp(1.0, -55), 96);
+        // FP64: the truncated recurrences reach 2^-55.  FP32 plans (increment
+        // form, one FP64-residual refinement per line solve): the first solve
+        // needs float accuracy (2^-20; what it misses is in the residual) and
+        // the correction, a few bits (2^-12), so that
+        // |x - x*| <~ eps32 |x| + 2^-20 * 2^-12 |x|.
+        o.H = compute_warmup(o, N, P, pl->fp32 ? std::ldexp(1.0, -20) : std::ldexp(1.0, -55), 96);
+        o.Hc = pl->fp32 ? compute_warmup(o, N, P, std::ldexp(1.0, -12), 96) : o.H;
     }
     for (int dir = 0; dir < 2; ++dir)
         if ((st = build_scan_tables(pl, dir))) return st;
@@ -624,6 +645,7 @@ iga_status choose_schedule(iga_plan *pl, int dir, int lines, int wpl)
     sc.mm = mm;
     sc.wpl = wpl;
     sc.win = 0;
+    sc.col = 0;
     const int maxw = (!pl->fp32 && pl->P == 3 && mm >= 12) ? 8 : 16;   // wavefronts per workgroup
     if (lines <= 0) {
         // widest workgroup (<= 16 wavefronts) that fits LDS and still gives
@@ -648,7 +670,7 @@ iga_status choose_schedule(iga_plan *pl, int dir, int lines, int wpl)
     }
     sc.lines = lines;
     iga_status st;
-    if (old.wpl != sc.wpl || old.mm != sc.mm || old.win)
+    if (old.wpl != sc.wpl || old.mm != sc.mm || old.win || old.col)
         if ((st = build_scan_tables(pl, dir))) return st;
     return sweep_prepare(pl, dir);
 }
@@ -692,12 +714,34 @@ iga_status choose_window_schedule(iga_plan *pl, int dir, int lines, int mm)
     sc.wpl = wpl;
     sc.mm = mm;
     sc.win = 1;
+    sc.col = 0;
     iga_status st = build_window_tables(pl, dir);
     if (!st) st = wsweep_prepare(pl, dir);
     if (st) {
         sc = old;
         return st;
     }
+    return IGA_OK;
+}
+
+// Column-wave schedule of the x-lines (FP32 plans): chunks of mm rows in
+// {16, 32} (0: 32), one line per lane.  IGA_EUNSUPPORTED if the plan is not
+// FP32 or its x operators decay too slowly for the kernel's warm-ups.
+iga_status choose_column_schedule(iga_plan *pl, int mm)
+{
+    if (mm <= 0) mm = 32;
+    if (!csweep_rows_ok(mm)) return fail(IGA_EINVAL, "rows per chunk must be 16 or 32");
+    if (!csweep_ok(pl))
+        return fail(IGA_EUNSUPPORTED, "column-wave solves need an FP32 plan whose x operators decay "
+                                      "within the kernel's warm-ups");
+    if ((size_t)pl->Nx * pl->Ny * 4 >= ((size_t)1 << 31))
+        return fail(IGA_EUNSUPPORTED, "column-wave solves address fields below 2 GiB");
+    Schedule &sc = pl->sched[0];
+    sc.lines = 1;
+    sc.wpl = 1;
+    sc.mm = mm;
+    sc.win = 0;
+    sc.col = 1;
     return IGA_OK;
 }
 

@@ -220,6 +220,10 @@ static iga_status build_wparams(const iga_plan *pl, int dir, const SweepJob *job
 iga_status launch_sweep(const iga_plan *pl, int dir, const SweepJob *jobs, int njobs, hipStream_t s)
 {
     const Schedule &sc = pl->sched[dir];
+    if (sc.col) {
+        if (dir != 0) return fail(IGA_EINVAL, "column-wave schedules are for x-lines");
+        return launch_csweep(pl, jobs, njobs, s);
+    }
     if (sc.win) {
         WSweepFn fn = pick_wfn(pl->fp32, pl->P, sc.mm, dir == 1);
         if (!fn) return fail(IGA_EUNSUPPORTED, "windowed line-solve kernel not compiled for this schedule");
@@ -259,6 +263,7 @@ iga_status build_sweep_batch(const std::vector<iga_plan *> &pls, int dir,
     for (size_t m0 = 0; m0 < pls.size(); ++m0) {
         if (done[m0]) continue;
         const Schedule key = pls[m0]->sched[dir];
+        if (key.col) return fail(IGA_EUNSUPPORTED, "column-wave schedules are not batched");
         std::vector<SweepParams> prms;
         std::vector<WSweepParams> wprms;
         std::vector<int2> info;

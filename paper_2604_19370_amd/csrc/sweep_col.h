@@ -1,0 +1,384 @@
+// sweep_col.h -- x-line solves with one line per lane ("column waves").
+//
+// The x-lines of a field (fixed column j, rows i = 0 .. Nx-1, dof (i, j) at
+// i*Ny + j) are strided in memory.  Here a wavefront owns 64 consecutive
+// columns -- one line per lane -- and a chunk of MM rows of them, so every row
+// it touches is one coalesced 256-byte access, and no lane ever needs another
+// lane's data: there is no LDS and no barrier.  All lanes work on the same
+// row at the same time, so the factor coefficients are wavefront-uniform and
+// live in scalar registers (one set for chunks whose rows are all canonical,
+// per-row scalar loads near the line ends).
+//
+// The solve is the banded LU of Section 4 restarted from a zero state outside
+// the chunk, as in the windowed kernels (the recurrences contract
+// geometrically, by less than 2^-20 over HH rows and 2^-12 over HC rows for
+// the operators this kernel accepts; the plan checks).  FP32 refined solve of
+// the chunk [r0, r0 + MM):
+//   1. x0 = LU^{-1} b on [r0 - HC - P, r0 + MM + HC + P): forward from a zero
+//      state HH rows before that range and on through HH rows after it, then
+//      backward from the top;
+//   2. r = b - A x0 in double on [r0 - HC, r0 + MM + HC);
+//   3. d = LU^{-1} r on [r0, r0 + MM) with HC-row warm-ups;
+//   4. x = x0 + d.
+// Neighbouring waves recompute the overlapping halo rows (read from L2); the
+// result is written out of place (dst != src), since other waves still read
+// the input rows around a chunk.
+#pragma once
+#include "sweep_kernels.h"
+
+namespace iga {
+
+constexpr int CMAXJOBS = 2;
+
+struct CSweepOp {
+    const float *rows;    // compressed factor rows [nrows][RS] (L, 1/U, U/U_rr)
+    const double *a64;    // compressed operator rows [nrows][RS] (A(r, r-P .. r+P))
+    int K0, NK, ID;       // rows [0, K0) and [NK, N) stored; interior -> row K0; ID identity row
+};
+
+struct CSweepJob {
+    const float *src;
+    float *dst;
+    int zero_skip;        // all-zero input window -> write zeros, skip the solve
+    CSweepOp op;
+};
+
+struct CSweepParams {
+    CSweepJob jobs[CMAXJOBS];
+    int N;         // line length (Nx)
+    int nlines;    // lines (Ny)
+    int ld;        // row stride of the field (Ny)
+    int ncg;       // column groups of 64 lines
+    int nchunks;   // chunks of MM rows per line
+    int njobs;
+};
+
+template <int P> struct ColHalo;
+template <> struct ColHalo<1> { static constexpr int HH = 12, HC = 8; };
+template <> struct ColHalo<2> { static constexpr int HH = 20, HC = 12; };
+template <> struct ColHalo<3> { static constexpr int HH = 28, HC = 20; };
+
+// table row of line row r (identity outside [0, N)), without branches
+__device__ __forceinline__ int col_row(int r, int N, const CSweepOp &o)
+{
+    const int in = min(r, o.K0) + max(0, r - o.NK + 1);
+    return (r >= 0 && r < N) ? in : o.ID;
+}
+
+// The tables are read-only during a launch: read them through the constant
+// address space, so uniform reads are scalar loads even after the kernel's
+// own stores.
+template <typename T>
+__device__ __forceinline__ const __attribute__((address_space(4))) T *col_const(const T *p)
+{
+    return (const __attribute__((address_space(4))) T *)p;
+}
+
+// factor coefficients of one row: l[j] = L(r, r-1-j), ui = 1/U(r,r),
+// u[j] = U(r, r+1+j)/U(r,r); a[j] = A(r, r-P+j)
+template <int P> struct ColCoef {
+    float l[P], ui, u[P];
+};
+template <int P> struct ColA {
+    double a[2 * P + 1];
+};
+
+template <int P>
+__device__ __forceinline__ ColCoef<P> col_coef(const CSweepOp &o, int idx)
+{
+    constexpr int RS = 2 * P + 2;
+    const auto c = col_const(o.rows) + (size_t)idx * RS;
+    ColCoef<P> k;
+#pragma unroll
+    for (int j = 0; j < P; ++j) k.l[j] = c[j];
+    k.ui = c[P];
+#pragma unroll
+    for (int j = 0; j < P; ++j) k.u[j] = c[P + 1 + j];
+    return k;
+}
+
+template <int P>
+__device__ __forceinline__ ColA<P> col_a(const CSweepOp &o, int idx)
+{
+    constexpr int RS = 2 * P + 2;
+    const auto c = col_const(o.a64) + (size_t)idx * RS;
+    ColA<P> k;
+#pragma unroll
+    for (int j = 0; j < 2 * P + 1; ++j) k.a[j] = c[j];
+    return k;
+}
+
+// Rows are streamed from global memory in blocks of CB rows with loads
+// issued two blocks ahead; a compiler barrier between blocks keeps every load
+// of the fully unrolled passes from being hoisted to the top (which would
+// need a register per row).
+constexpr int CB = 8;
+
+__device__ __forceinline__ void col_fence()
+{
+    __builtin_amdgcn_sched_barrier(0);
+    asm volatile("" ::: "memory");
+}
+
+// The same, and the values in v must be computed before it: keeps a block's
+// arithmetic from sinking below the next block's loads.
+template <int K>
+__device__ __forceinline__ void col_fence_on(float (&v)[K])
+{
+#pragma unroll
+    for (int i = 0; i < K; ++i) asm volatile("" : "+v"(v[i]) :: "memory");
+    __builtin_amdgcn_sched_barrier(0);
+}
+
+// b values of rows first .. first + CB - 1 of this lane's column (0 outside
+// [0, N)).  Buffer loads: the lane's column (clamped to a valid one) is the
+// per-lane byte offset, the row (clamped to [0, N)) a uniform scalar offset,
+// so every access is in bounds and needs no per-lane address register; the
+// uniform range test scales the value (a select on a loaded value lets the
+// compiler branch around each load).
+__device__ __forceinline__ void col_load_block(float (&v)[CB], __amdgpu_buffer_rsrc_t rs, int voff,
+                                               int first, int N, int ld)
+{
+    // the block's row is pinned here, so the scalar offsets of every block
+    // are not all computed (and kept) up front
+    asm volatile("" : "+s"(first));
+#pragma unroll
+    for (int u = 0; u < CB; ++u) {
+        const int r = first + u;
+        const int rc = min(max(r, 0), N - 1);
+        const float in = __int_as_float((r >= 0 && r < N) ? 0x3f800000 : 0);
+        // the builtin returns the raw 32 bits
+        v[u] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, voff, rc * ld * 4, 0)) * in;
+    }
+}
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t col_rsrc(const float *p, int N, int ld)
+{
+    // raw buffer over the field: num_records in bytes, default word 3
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<float *>(p), (short)0, N * ld * 4,
+                                             0x00020000);
+}
+
+// The refined solve of one chunk for this lane's column.  CANON: every row
+// in reach uses the canonical coefficients (passed in kc, ka).
+// ZS (zero-skip jobs): the first forward pass also tests its input; a
+// wavefront whose whole input window is zero stores zeros and stops (the
+// solve of zero data is exactly zero).
+template <int P, int MM, bool CANON, bool ZS>
+__device__ __forceinline__ void col_solve(const CSweepParams &prm, const CSweepJob &job,
+                                          __amdgpu_buffer_rsrc_t rs, int r0, int j, bool jok,
+                                          const ColCoef<P> &kc, const ColA<P> &ka)
+{
+    constexpr int HH = ColHalo<P>::HH, HC = ColHalo<P>::HC;
+    constexpr int NY = MM + 2 * (HC + P) + HH;   // rows kept from the first forward pass
+    constexpr int NR = MM + 2 * HC;              // rows of the residual / correction
+    constexpr int NF = HH + NY;                  // rows of the first forward pass
+    constexpr int NFB = (NF + CB - 1) / CB, NRB = (NR + CB - 1) / CB;
+    const int N = prm.N, ld = prm.ld;
+    const CSweepOp &o = job.op;
+    const int voff = min(j, prm.nlines - 1) * 4;   // in bounds for every lane
+    // per-row coefficients near the line ends: the row is pinned where it is
+    // used, so the scalar loads are not all issued (and held) up front
+    auto coef = [&](int r) -> ColCoef<P> {
+        if constexpr (CANON) {
+            return kc;
+        } else {
+            asm volatile("" : "+s"(r));
+            return col_coef<P>(o, col_row(r, N, o));
+        }
+    };
+    auto acoef = [&](int r) -> ColA<P> {
+        if constexpr (CANON) {
+            return ka;
+        } else {
+            asm volatile("" : "+s"(r));
+            return col_a<P>(o, col_row(r, N, o));
+        }
+    };
+
+    // 1. first solve: forward over HH warm-up rows, then NY kept rows
+    const int ry = r0 - HC - P;   // row of y[0]
+    const int rf = ry - HH;       // first row of the forward pass
+    float s[P];
+#pragma unroll
+    for (int q = 0; q < P; ++q) s[q] = 0.0f;
+    float y[NY];
+    bool nz = false;
+    {
+        float bb[3][CB];
+        col_load_block(bb[0], rs, voff, rf, N, ld);
+        if (NFB > 1) col_load_block(bb[1], rs, voff, rf + CB, N, ld);
+#pragma unroll
+        for (int blk = 0; blk < NFB; ++blk) {
+            if (blk + 2 < NFB) col_load_block(bb[(blk + 2) % 3], rs, voff, rf + (blk + 2) * CB, N, ld);
+            col_fence();
+#pragma unroll
+            for (int u = 0; u < CB; ++u) {
+                const int i = blk * CB + u;   // row rf + i
+                if (i < NF) {
+                    const ColCoef<P> c = coef(rf + i);
+                    float v = bb[blk % 3][u];
+                    if constexpr (ZS) nz = nz || v != 0.0f;
+#pragma unroll
+                    for (int q = P - 1; q >= 0; --q) v -= c.l[q] * s[q];
+#pragma unroll
+                    for (int q = P - 1; q > 0; --q) s[q] = s[q - 1];
+                    s[0] = v;
+                    if (i >= HH) y[i - HH] = v;
+                }
+            }
+            col_fence_on(s);
+        }
+    }
+    if constexpr (ZS) {
+        if (!__any(nz)) {
+            if (jok) {
+                float *dst = job.dst + j;
+#pragma unroll
+                for (int k = 0; k < MM; ++k)
+                    if (r0 + k < N) dst[(size_t)(r0 + k) * ld] = 0.0f;
+            }
+            return;
+        }
+    }
+    // backward from the top: rows NY - HH .. NY - 1 are the warm-up
+    float t[P];
+#pragma unroll
+    for (int q = 0; q < P; ++q) t[q] = 0.0f;
+#pragma unroll
+    for (int k = NY - 1; k >= 0; --k) {
+        const ColCoef<P> c = coef(ry + k);
+        float v = y[k] * c.ui;
+#pragma unroll
+        for (int q = P - 1; q >= 0; --q) v -= c.u[q] * t[q];
+#pragma unroll
+        for (int q = P - 1; q > 0; --q) t[q] = t[q - 1];
+        t[0] = v;
+        y[k] = v;   // x0 for k < NY - HH
+    }
+    // 2. residual in double on rows r0 - HC .. r0 + MM + HC - 1 (x0 at row
+    //    r - P + q is y[m + q]), over a sliding window of 2P+1 doubles; each
+    //    conversion is pinned to the block that consumes it
+    const int rr0 = r0 - HC;
+    float rr[NR];
+    {
+        double w[2 * P + 1];
+#pragma unroll
+        for (int q = 0; q < 2 * P; ++q) w[q + 1] = (double)y[q];
+        float bb[3][CB];
+        col_load_block(bb[0], rs, voff, rr0, N, ld);
+        if (NRB > 1) col_load_block(bb[1], rs, voff, rr0 + CB, N, ld);
+#pragma unroll
+        for (int blk = 0; blk < NRB; ++blk) {
+            if (blk + 2 < NRB) col_load_block(bb[(blk + 2) % 3], rs, voff, rr0 + (blk + 2) * CB, N, ld);
+            col_fence();
+#pragma unroll
+            for (int u = 0; u < CB; ++u) {
+                const int m = blk * CB + u;
+                if (m < NR) {
+                    float yn = y[m + 2 * P];
+                    asm volatile("" : "+v"(yn));
+#pragma unroll
+                    for (int q = 0; q < 2 * P; ++q) w[q] = w[q + 1];
+                    w[2 * P] = (double)yn;
+                    const ColA<P> a = acoef(rr0 + m);
+                    double acc = (double)bb[blk % 3][u];
+#pragma unroll
+                    for (int q = 0; q < 2 * P + 1; ++q) acc -= a.a[q] * w[q];
+                    rr[m] = (float)acc;
+                }
+            }
+            float last[1] = {rr[min(blk * CB + CB - 1, NR - 1)]};
+            col_fence_on(last);
+            rr[min(blk * CB + CB - 1, NR - 1)] = last[0];
+        }
+    }
+    // 3. correction: forward from r0 - HC, backward from r0 + MM + HC - 1
+#pragma unroll
+    for (int q = 0; q < P; ++q) s[q] = 0.0f;
+#pragma unroll
+    for (int m = 0; m < NR; ++m) {
+        const ColCoef<P> c = coef(rr0 + m);
+        float v = rr[m];
+#pragma unroll
+        for (int q = P - 1; q >= 0; --q) v -= c.l[q] * s[q];
+#pragma unroll
+        for (int q = P - 1; q > 0; --q) s[q] = s[q - 1];
+        s[0] = v;
+        rr[m] = v;
+    }
+#pragma unroll
+    for (int q = 0; q < P; ++q) t[q] = 0.0f;
+#pragma unroll
+    for (int m = NR - 1; m >= HC; --m) {
+        const ColCoef<P> c = coef(rr0 + m);
+        float v = rr[m] * c.ui;
+#pragma unroll
+        for (int q = P - 1; q >= 0; --q) v -= c.u[q] * t[q];
+#pragma unroll
+        for (int q = P - 1; q > 0; --q) t[q] = t[q - 1];
+        t[0] = v;
+        rr[m] = v;
+    }
+    // 4. x = x0 + d on the own rows
+    if (jok) {
+        float *dst = job.dst + j;
+#pragma unroll
+        for (int k = 0; k < MM; ++k) {
+            const int r = r0 + k;
+            if (r < N) dst[(size_t)r * ld] = y[HC + P + k] + rr[HC + k];
+        }
+    }
+}
+
+// One wavefront: column group and chunk quad from the block index (XCD-aware
+// order), chunk 4*quad + wave, job blockIdx.y.
+template <int P, int MM>
+__device__ __forceinline__ void csweep_body(const CSweepParams &prm)
+{
+    constexpr int HH = ColHalo<P>::HH, HC = ColHalo<P>::HC;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    // blocks dispatched to one XCD take consecutive chunk quads of a column
+    // group, so the halo rows two quads share are in that XCD's L2
+    const int nq = (prm.nchunks + 3) >> 2;
+    const int L = xcd_remap(blockIdx.x, gridDim.x);
+    const int cg = L / nq;
+    const int chunk = (L - cg * nq) * 4 + wave;
+    if (chunk >= prm.nchunks) return;   // whole wavefront
+    const CSweepJob &job = prm.jobs[blockIdx.y];
+    const int j = cg * 64 + lane;
+    const bool jok = j < prm.nlines;
+    const int r0 = chunk * MM;
+    const int N = prm.N;
+    // rows the first forward pass reads
+    const int rlo = r0 - HC - P - HH, rhi = r0 + MM + HC + P + HH;   // [rlo, rhi)
+    const CSweepOp &o = job.op;
+    // the buffer resource is built here, before the paths diverge, so it
+    // stays in scalar registers
+    const __amdgpu_buffer_rsrc_t rs = col_rsrc(job.src, N, prm.ld);
+    const bool canon = rlo >= o.K0 && rhi <= o.NK;
+    if (canon) {
+        const ColCoef<P> kc = col_coef<P>(o, o.K0);
+        const ColA<P> ka = col_a<P>(o, o.K0);
+        if (job.zero_skip) col_solve<P, MM, true, true>(prm, job, rs, r0, j, jok, kc, ka);
+        else col_solve<P, MM, true, false>(prm, job, rs, r0, j, jok, kc, ka);
+    } else {
+        col_solve<P, MM, false, false>(prm, job, rs, r0, j, jok, ColCoef<P>{}, ColA<P>{});
+    }
+}
+
+// occupancy target: 3 wavefronts per SIMD (at most 168 VGPRs) where the
+// chunk fits, else 2
+template <int P, int MM> struct ColWaves {
+    static constexpr int value = (P == 3 || MM == 32) ? 2 : 3;
+};
+
+template <int P, int MM>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(ColWaves<P, MM>::value)))
+void k_csweep(CSweepParams prm)
+{
+    csweep_body<P, MM>(prm);
+}
+
+}  // namespace iga

@@ -15,7 +15,10 @@
 // No scan and no cross-lane arithmetic: lanes only meet in LDS, at barriers.
 // Rows outside [0, N) are identity rows with zero data, so the line ends are
 // exact.  FP32 plans refine once: x0 = LU32^{-1} b, r = b - A64 x0 in double,
-// x = x0 + LU32^{-1} r (as in the exact kernels).
+// x = x0 + LU32^{-1} r (as in the exact kernels).  The correction solve runs
+// a shorter warm-up Hc <= H: its result is a small correction, needed to a
+// few bits only, and the first solve's truncation error is part of the
+// residual it corrects.
 //
 // Coefficients come from strip tables in LDS (see WinGeom): each lane reads
 // window row j of its table at base + j*RS, base fixed per lane, so the
@@ -53,19 +56,20 @@ template <typename T, int P, int MM> struct WinLane {
     int ab;       // base row of the mm-row windows (row r0)
 };
 
-// forward substitution: warm-up rows from `in` (line buffer, row r at in[r]),
-// then the lane's own rows in x
+// forward substitution: Hr <= H warm-up rows from `in` (line buffer, row r at
+// in[r]), then the lane's own rows in x; the factor window starts H rows
+// before the chunk
 template <typename T, int P, int MM>
 __device__ __forceinline__ void wfwd(T (&x)[MM], const T *__restrict__ in, const T *__restrict__ tab,
-                                     const WinLane<T, P, MM> &ln, int H)
+                                     const WinLane<T, P, MM> &ln, int H, int Hr)
 {
     constexpr int RS = RowStride<P>::RS;
     T s[P];
 #pragma unroll
     for (int j = 0; j < P; ++j) s[j] = T(0);
-    const T *d = in + ln.r0 - H;
-    const T *c = tab + (size_t)ln.wb * RS;
-    for (int j0 = 0; j0 < H; j0 += 4) {
+    const T *d = in + ln.r0 - Hr;
+    const T *c = tab + ((size_t)ln.wb + H - Hr) * RS;
+    for (int j0 = 0; j0 < Hr; j0 += 4) {
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
             const T *L = c + (j0 + u) * RS;
@@ -77,7 +81,7 @@ __device__ __forceinline__ void wfwd(T (&x)[MM], const T *__restrict__ in, const
             s[0] = y;
         }
     }
-    const T *co = c + (size_t)H * RS;
+    const T *co = tab + ((size_t)ln.wb + H) * RS;
 #pragma unroll
     for (int k = 0; k < MM; ++k) {
         const T *L = co + k * RS;
@@ -91,11 +95,11 @@ __device__ __forceinline__ void wfwd(T (&x)[MM], const T *__restrict__ in, const
     }
 }
 
-// backward substitution: warm-up rows of y after the chunk from `in`, then
-// the own rows
+// backward substitution: Hr <= H warm-up rows of y after the chunk from
+// `in`, then the own rows
 template <typename T, int P, int MM>
 __device__ __forceinline__ void wbwd(T (&x)[MM], const T *__restrict__ in, const T *__restrict__ tab,
-                                     const WinLane<T, P, MM> &ln, int H)
+                                     const WinLane<T, P, MM> &ln, int H, int Hr)
 {
     constexpr int RS = RowStride<P>::RS;
     T t[P];
@@ -103,7 +107,7 @@ __device__ __forceinline__ void wbwd(T (&x)[MM], const T *__restrict__ in, const
     for (int j = 0; j < P; ++j) t[j] = T(0);
     const T *d = in + ln.r0 + MM;
     const T *c = tab + ((size_t)ln.wb + H + MM) * RS + P;
-    for (int j0 = H - 4; j0 >= 0; j0 -= 4) {
+    for (int j0 = Hr - 4; j0 >= 0; j0 -= 4) {
 #pragma unroll
         for (int u = 3; u >= 0; --u) {
             const T *U = c + (j0 + u) * RS;
@@ -141,12 +145,12 @@ __device__ __forceinline__ void publish(T *buf, const T (&x)[MM], int r0)
 // On return `tmp` holds y and is still being read by other lanes.
 template <typename T, int P, int MM>
 __device__ __forceinline__ void wsolve(T (&x)[MM], const T *in, T *tmp, const T *tab,
-                                       const WinLane<T, P, MM> &ln, int H)
+                                       const WinLane<T, P, MM> &ln, int H, int Hr)
 {
-    wfwd<T, P, MM>(x, in, tab, ln, H);
+    wfwd<T, P, MM>(x, in, tab, ln, H, Hr);
     publish<T, MM>(tmp, x, ln.r0);
     __syncthreads();
-    wbwd<T, P, MM>(x, tmp, tab, ln, H);
+    wbwd<T, P, MM>(x, tmp, tab, ln, H, Hr);
 }
 
 // x <- A^{-1} x with one FP64-residual refinement for FP32 plans.  Entry:
@@ -155,16 +159,16 @@ __device__ __forceinline__ void wsolve(T (&x)[MM], const T *in, T *tmp, const T 
 template <typename T, int P, int MM>
 __device__ __forceinline__ void wsolve_refined(T (&x)[MM], T *bin, T *bout, const T *tab,
                                                const double *a64, const WinLane<T, P, MM> &ln,
-                                               int H)
+                                               int H, int Hc)
 {
     if constexpr (sizeof(T) == 8) {
-        wsolve<T, P, MM>(x, bin, bout, tab, ln, H);
+        wsolve<T, P, MM>(x, bin, bout, tab, ln, H, H);
     } else {
         constexpr int RS = RowStride<P>::RS;
         T b[MM];
 #pragma unroll
         for (int k = 0; k < MM; ++k) b[k] = x[k];
-        wsolve<T, P, MM>(x, bin, bout, tab, ln, H);   // bin read (warm-up), bout = y
+        wsolve<T, P, MM>(x, bin, bout, tab, ln, H, H);   // bin read (warm-up), bout = y
         // x0 -> bin: bin's last readers passed the barrier inside wsolve
         publish<T, MM>(bin, x, ln.r0);
         __syncthreads();
@@ -189,7 +193,7 @@ __device__ __forceinline__ void wsolve_refined(T (&x)[MM], T *bin, T *bout, cons
         publish<T, MM>(bout, b, ln.r0);
         __syncthreads();
         // correction: bin (x0) was last read by the residual, before that barrier
-        wsolve<T, P, MM>(b, bout, bin, tab, ln, H);
+        wsolve<T, P, MM>(b, bout, bin, tab, ln, H, Hc);
 #pragma unroll
         for (int k = 0; k < MM; ++k) x[k] += b[k];
     }
@@ -204,7 +208,7 @@ __device__ __forceinline__ void wsweep_body(const WSweepParams &prm, const int b
     constexpr bool F32 = sizeof(T) == 4;
     const SweepJob job = prm.jobs[jobi];
     const WinGeom &g = prm.g;
-    const int H = g.H;
+    const int H = g.H, Hc = g.Hc;
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -363,7 +367,7 @@ __device__ __forceinline__ void wsweep_body(const WSweepParams &prm, const int b
     }
     // A: input published; B: free
     if (has0) {
-        wsolve_refined<T, P, MM>(x, A, B, tab0, a640, ln, H);
+        wsolve_refined<T, P, MM>(x, A, B, tab0, a640, ln, H, Hc);
         __syncthreads();
     }
     if (job.base) {
@@ -399,7 +403,7 @@ __device__ __forceinline__ void wsweep_body(const WSweepParams &prm, const int b
         publish<T, MM>(B, y, ln.r0);
         __syncthreads();
         if (has1) {
-            wsolve_refined<T, P, MM>(y, B, A, tab1, a641, ln, H);
+            wsolve_refined<T, P, MM>(y, B, A, tab1, a641, ln, H, Hc);
             __syncthreads();
         }
         if (job.add_after) {

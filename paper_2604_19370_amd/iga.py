@@ -28,7 +28,7 @@ EXPORTED = ("iga_default_coeffs", "iga_plan_create", "iga_plan_destroy", "iga_pl
             "iga_ensemble_size", "iga_ensemble_launches", "iga_ensemble_step", "iga_ensemble_run",
             "iga_ensemble_set_schedule", "iga_ensemble_set_window_schedule",
             "iga_ensemble_set_assembly_rows", "iga_ensemble_autotune", "iga_step_forced",
-            "iga_plan_quadrature_points", "iga_last_error")
+            "iga_plan_quadrature_points", "iga_plan_set_column_schedule", "iga_last_error")
 
 _COEFF_NAMES = ("c_adv", "c_diff", "c_react", "c_nld", "c_ign", "t_ig", "fuel_thr", "t_act",
                 "c_forcing", "c_rad", "fuel_rate")
@@ -106,6 +106,7 @@ def lib() -> ctypes.CDLL:
         L.iga_ensemble_set_assembly_rows.argtypes = [vp, i32]
         L.iga_ensemble_autotune.argtypes = [vp, pp, pp, i32, vp]
         L.iga_step_forced.argtypes = [vp, vp, vp, vp, vp, vp]
+        L.iga_plan_set_column_schedule.argtypes = [vp, i32]
         L.iga_plan_quadrature_points.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_double)]
         L.iga_last_error.argtypes = []
         L.iga_last_error.restype = ctypes.c_char_p
@@ -290,11 +291,15 @@ class Plan:
         _check(lib().iga_plan_set_window_schedule(self._h, int(dir), int(lines), int(rows_per_lane)),
                "iga_plan_set_window_schedule")
 
+    def set_column_schedule(self, rows_per_chunk=0):
+        _check(lib().iga_plan_set_column_schedule(self._h, int(rows_per_chunk)),
+               "iga_plan_set_column_schedule")
+
     def solver(self, dir):
         w, h = ctypes.c_int32(), ctypes.c_int32()
         _check(lib().iga_plan_solver(self._h, int(dir), ctypes.byref(w), ctypes.byref(h)),
                "iga_plan_solver")
-        return dict(windowed=bool(w.value), warmup=h.value)
+        return dict(windowed=bool(w.value), warmup=h.value, column=w.value == 2)
 
 
 class Ensemble:

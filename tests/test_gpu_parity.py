@@ -143,6 +143,75 @@ def test_stiff_operators_fall_back_to_exact_solves():
     assert rel(host(T), To) < TOL64 and rel(host(F), Fo) < TOL64
 
 
+COLUMN_SHAPES = [(150, 133), (600, 70), (37, 290), (1000, 65)]
+
+
+@pytest.mark.parametrize("p", [1, 2, 3])
+@pytest.mark.parametrize("mm", [16, 32])
+@pytest.mark.parametrize("nx,ny", COLUMN_SHAPES + [(0, 0)])
+def test_line_solve_column_schedule(p, mm, nx, ny):
+    """Column waves (one x-line per lane, own warm-ups on both sides of each
+    chunk): x-line solves of FP32 plans match the oracle to the refined FP32
+    tolerance, with ragged column groups and chunks, lines shorter than one
+    chunk and the minimum mesh; the CN operator product (which 2) is refused."""
+    if nx == 0:   # the minimum mesh
+        nx = ny = 2 * p + 1
+    print(f"column schedule {nx}x{ny} p{p} mm{mm}", flush=True)
+    sc = inputs.small_case(40 + p, nx, ny, p, "strang")
+    pl, od = plan_and_oracle(sc, "fp32")
+    pl.set_column_schedule(mm)
+    assert pl.solver(0)["column"] and pl.schedule(0)["rows_per_lane"] == mm
+    X = np.random.default_rng(nx + ny).standard_normal((nx + p, ny + p))
+    for which in (0, 1):
+        x = dev(X, True)
+        pl.line_solve(0, which, x)
+        assert rel(host(x), oracle.line_solve(od, 0, which, X)) < TOL32, which
+    with pytest.raises(iga.IgaError) as e:
+        pl.line_solve(0, 2, dev(X, True))
+    assert e.value.status == iga.EUNSUPPORTED
+    # y-lines are unaffected
+    x = dev(X, True)
+    pl.line_solve(1, 1, x)
+    assert rel(host(x), oracle.line_solve(od, 1, 1, X)) < TOL32
+    pl.close()
+
+
+def test_column_schedule_refused_for_fp64():
+    sc = inputs.small_case(3, 40, 40, 2, "pr")
+    pl, _ = plan_and_oracle(sc, "fp64")
+    with pytest.raises(iga.IgaError) as e:
+        pl.set_column_schedule(16)
+    assert e.value.status == iga.EUNSUPPORTED
+    pl.close()
+
+
+@pytest.mark.parametrize("nx,ny,p,scheme", [c for c in CASES if c[0] >= 5])
+@pytest.mark.parametrize("mm", [16, 32])
+def test_steps_fp32_column_schedule(nx, ny, p, scheme, mm):
+    """Whole FP32 steps with column-wave x sweeps (out of place, into the
+    second scratch fields; the fuel job writes zeros where its input window
+    is zero): per-step parity with the oracle, and graph replays equal eager
+    steps bitwise."""
+    print(f"steps fp32 column {nx}x{ny} p{p} {scheme} mm{mm}", flush=True)
+    sc = inputs.small_case(500 + nx, nx, ny, p, scheme, dt=2e-3)
+    pl, od = plan_and_oracle(sc, "fp32")
+    pl.set_column_schedule(mm)
+    t, f = dev(sc.T0, True), dev(sc.fuel0, True)
+    for k in range(3):
+        T0, F0 = host(t), host(f)
+        T, F = oracle.step(od, T0, F0)
+        pl.step(t, f)
+        assert rel(host(t), T) < TOL32, k
+        assert rel(host(f), F) < TOL32, k
+    t2, f2 = dev(sc.T0, True), dev(sc.fuel0, True)
+    for _ in range(3):
+        pl.step(t2, f2)
+    t3, f3 = dev(sc.T0, True), dev(sc.fuel0, True)
+    pl.run(t3, f3, 3)
+    assert torch.equal(t2, t3) and torch.equal(f2, f3)
+    pl.close()
+
+
 def test_line_solve_fp32_refined_accuracy():
     """FP32 solve + one FP64-residual refinement: error near float rounding of the
     result, well below an unrefined FP32 solve's cond * eps."""
