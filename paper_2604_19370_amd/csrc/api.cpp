@@ -457,7 +457,7 @@ iga_status iga_autotune(iga_plan *plan, const void *T, const void *fuel, int32_t
     {
         int best = plan->asm_rows;
         float best_ms = 1e30f;
-        for (int rows : {4, 8, 16, 32, 64}) {
+        for (int rows : ASSEMBLY_ROW_CANDIDATES) {
             if (rows > plan->Nx && rows != 4) continue;
             plan->asm_rows = rows;
             float ms = time_launches(s, reps, [&] { return launch_assemble(plan, 0, T, fuel, R, RF, s); });

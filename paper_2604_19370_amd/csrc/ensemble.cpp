@@ -311,7 +311,7 @@ iga_status iga_ensemble_autotune(iga_ensemble *ens, void *const *T, void *const 
     {
         int best = ens->plans[0]->asm_rows;
         float best_ms = 1e30f;
-        for (int rows : {4, 8, 16, 32, 64}) {
+        for (int rows : ASSEMBLY_ROW_CANDIDATES) {
             if ((st = iga_ensemble_set_assembly_rows(ens, rows)) || (st = bind(ens, T, fuel))) return st;
             float ms = time_launches(s, reps, [&] { return launch_batch(ens->a1, s); });
             if (ms >= 0 && ms < best_ms) {

@@ -262,6 +262,12 @@ iga_status wsweep_prepare(const iga_plan *pl, int dir);
 iga_status launch_nonfinite(const iga_plan *pl, const void *T, const void *fuel, int *flag,
                             hipStream_t s);
 
+// Element rows marched per assembly wavefront that the autotuners try.  The
+// list is fine-grained because the kernel time is set by the most loaded
+// compute unit: on small meshes one more row per wavefront can remove a whole
+// extra round of workgroups from some compute units.
+#define ASSEMBLY_ROW_CANDIDATES {4, 5, 6, 7, 8, 9, 10, 11, 12, 14, 16, 20, 24, 28, 32, 40, 48, 64}
+
 // the launches of one step of a plan on fields (T, fuel) (api.cpp)
 struct StepPhases {
     AsmArgs a1, a2;
