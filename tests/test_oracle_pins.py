@@ -3,7 +3,9 @@
 Each test checks the oracle against something other than itself: closed forms,
 library routines (numpy / scipy / LAPACK), dense brute force on tiny grids, and
 invariants of the scheme (fixed points, conservation, exact amplification
-factors of discrete eigenmodes, reflection symmetry).
+factors of discrete eigenmodes, reflection symmetry), the temporal orders of
+the schemes on linear problems, and boundedness of the full model where the
+paper leaves constants open.
 """
 import json
 import os
@@ -490,3 +492,57 @@ def test_step_flagged_marks_ambiguous_ignition_decisions(scheme):
     expect = np.zeros((nx, ny), dtype=bool)
     expect[5:8, 4:6] = True
     assert np.array_equal(fl, expect)
+
+
+# ---------------------------------------------------------------------------
+# temporal order and the unpinned constants
+# ---------------------------------------------------------------------------
+def _linear_runs(scheme, tend, ks):
+    """Advection-diffusion-reaction (constant implicit wind, no F) from a
+    smooth bump, to t = tend with dt = tend / 2^k."""
+    n, p, L = 24, 2, 24.0
+    g = inputs.greville(n, p) * L
+    T0 = 300 + 200 * np.exp(-((g[:, None] - 10) ** 2 + (g[None, :] - 14) ** 2) / 20.0)
+    out = {}
+    for k in ks:
+        d = oracle.make_desc(n, n, p, L, L, tend / 2 ** k, scheme,
+                             coeffs=SOURCES_OFF | {"c_diff": 0.5, "c_react": -0.3},
+                             wind=dict(kind="const", bx=0.8, by=-0.4))
+        out[k], _ = oracle.run(d, T0, np.ones_like(T0), 2 ** k)
+    return out
+
+
+@pytest.mark.parametrize("scheme", ["pr", "strang"])
+def test_split_schemes_are_second_order_on_linear_problems(scheme):
+    """Peaceman-Rachford and Strang with Crank-Nicolson substeps are second
+    order in time when F is absent (Sections 3.1, 3.2)."""
+    sol = _linear_runs(scheme, 2.0, range(3, 9))
+    errs = [np.linalg.norm(sol[k] - sol[8]) for k in range(3, 7)]
+    orders = [np.log2(a / b) for a, b in zip(errs, errs[1:])]
+    assert all(1.8 < o < 2.3 for o in orders), orders
+
+
+def test_explicit_scheme_is_first_order_on_linear_problems():
+    sol = _linear_runs("explicit", 0.5, range(4, 11))
+    errs = [np.linalg.norm(sol[k] - sol[10]) for k in range(4, 8)]
+    orders = [np.log2(a / b) for a, b in zip(errs, errs[1:])]
+    assert all(0.9 < o < 1.3 for o in orders), orders
+
+
+def test_full_model_stays_bounded_and_converges_under_dt_halving():
+    """C_ign and fuel_rate are not given by the paper (parity unpinned); the
+    full model with the chosen values stays finite and below 2400 K, the fuel
+    below its initial maximum plus the projection's overshoot, and halving dt
+    brings the state closer to the finest run."""
+    sc = inputs.small_case(77, 40, 40, 2, "strang", dt=1e-3, filtered=True)
+    res = {}
+    for dt in (2e-3, 1e-3, 5e-4):
+        d = oracle.make_desc(40, 40, 2, 40.0, 40.0, dt, "strang", wind=sc.wind_dict())
+        T, F = oracle.run(d, sc.T0, sc.fuel0, int(round(0.2 / dt)))
+        assert np.isfinite(T).all() and np.isfinite(F).all()
+        assert T.max() < 2400.0
+        assert F.max() < 1.5 * sc.fuel0.max()
+        res[dt] = T
+    a = np.linalg.norm(res[2e-3] - res[5e-4])
+    b = np.linalg.norm(res[1e-3] - res[5e-4])
+    assert a / b > 1.5, (a, b)
