@@ -298,10 +298,25 @@ def cpu_baseline(sc, budget_s):
     el = time.perf_counter() - t0
     n_total = n + 1
     el_total = el + one
+    # the same oracle on one core, over the next steps of the run (bounded to
+    # a few seconds)
+    oracle.set_threads(1)
+    try:
+        t0 = time.perf_counter()
+        T1, F1 = oracle.step(d, T, F)
+        k1, el1 = 1, time.perf_counter() - t0
+        while el1 < min(4.0, budget_s / 3):
+            t0 = time.perf_counter()
+            T1, F1 = oracle.step(d, T1, F1)
+            k1, el1 = k1 + 1, el1 + time.perf_counter() - t0
+    finally:
+        oracle.set_threads(threads)
     return {"value": sc.ndof * n_total / el_total, "unit": "DOF-steps/s", "cores": threads,
             "kind": "oracle",
             "sample": f"{sc.nel_x}x{sc.nel_y} p={sc.p} Strang-CN FP64, first {n_total} of "
-                      f"{sc.steps} steps ({el_total:.1f} s, {threads} OpenMP threads)"}
+                      f"{sc.steps} steps ({el_total:.1f} s, {threads} OpenMP threads)",
+            "value_1core": sc.ndof * k1 / el1,
+            "sample_1core": f"steps {n_total + 1}-{n_total + k1} on one OpenMP thread ({el1:.1f} s)"}
 
 
 def main():
