@@ -59,7 +59,8 @@ iga_status launch_csweep(const iga_plan *pl, const SweepJob *jobs, int njobs, hi
         prm.jobs[i].zero_skip = j.zero_skip;
         prm.jobs[i].op.rows = pl->op_rows[j.op0].as<float>();
         prm.jobs[i].op.a64 = pl->op_a64c[j.op0].as<double>();
-        prm.jobs[i].op.K0 = std::min(o.K0, o.nrows - 2);
+        // compressed rows: [0, K0), the canonical row K0, [NK, N), identity
+        prm.jobs[i].op.K0 = o.K0;
         prm.jobs[i].op.NK = o.NK;
         prm.jobs[i].op.ID = o.nrows - 1;
     }
