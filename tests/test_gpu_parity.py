@@ -136,7 +136,7 @@ def test_stiff_operators_fall_back_to_exact_solves():
     sc = inputs.small_case(9, 200, 36, 2, "pr", dt=400.0)
     pl, od = plan_and_oracle(sc, "fp64", coeffs=dict(c_nld=0.0, c_ign=0.0, c_rad=0.0,
                                                       c_forcing=0.0))
-    assert pl.solver(0) == {"windowed": False, "warmup": 0}
+    assert pl.solver(0) == {"windowed": False, "warmup": 0, "column": False}
     T, F = dev(sc.T0), dev(sc.fuel0)
     pl.step(T, F)
     To, Fo = oracle.step(od, sc.T0, sc.fuel0)
