@@ -325,8 +325,17 @@ __device__ __forceinline__ void assemble_body(const AsmParams<T> &a, const int g
     }
 }
 
+// Occupancy target: float cubic kernels sit a few registers above the 256
+// that allow two wavefronts per SIMD; asking for two costs a couple of
+// spilled registers and doubles the wavefronts in flight.  Elsewhere the
+// compiler's own allocation stands.
+template <typename T, int P> struct AsmWaves {
+    static constexpr int value = (sizeof(T) == 4 && P == 3) ? 2 : 1;
+};
+
 template <typename T, int P, bool FUEL, bool SRC>
-__global__ __launch_bounds__(256) void k_assemble(AsmParams<T> a)
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(AsmWaves<T, P>::value)))
+void k_assemble(AsmParams<T> a)
 {
     const int gw = blockIdx.x * (blockDim.x >> 6) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     if (gw >= a.nstrips * a.ntiles) return;
@@ -336,8 +345,8 @@ __global__ __launch_bounds__(256) void k_assemble(AsmParams<T> a)
 // Batched launch over the members of an ensemble: wavefront w does wavefront
 // info[w].y of member info[w].x (x < 0: no work).
 template <typename T, int P, bool FUEL>
-__global__ __launch_bounds__(256) void k_assemble_batch(const AsmParams<T> *__restrict__ prms,
-                                                        const int2 *__restrict__ info)
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(AsmWaves<T, P>::value)))
+void k_assemble_batch(const AsmParams<T> *__restrict__ prms, const int2 *__restrict__ info)
 {
     const int gw = blockIdx.x * (blockDim.x >> 6) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int2 wi = info[gw];
