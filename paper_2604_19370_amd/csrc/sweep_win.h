@@ -221,6 +221,89 @@ __device__ __forceinline__ void wsweep_body(const WSweepParams &prm, const int b
     const int lw = wave / WPL;
     const int part = wave - lw * WPL;
 
+    // Stage W lines of a field into buffer `buf` (row r of line l at
+    // buf[l*Lb + H + r]) and back.  A thread moves at most MM values of a
+    // line (64*WPL*MM >= N): all its loads are issued before the first store,
+    // so a staging costs one memory latency, not one per pass.  y-lines: the
+    // WPL wavefronts of a line copy its contiguous run of N values, 64
+    // consecutive values per wavefront and instruction.  x-lines: rows of W
+    // consecutive columns; a workgroup slot past the last line copies a live
+    // column into its own (unused) buffer.
+    const int jcol = tid & (W - 1), r00 = tid >> wlog;
+    const int yi0 = part * 64 + lane, ystep = 64 * WPL;
+    auto fetch_lines = [&](const T *src, T(&v)[MM]) {
+        if constexpr (DIRY) {
+            const T *s = src + (size_t)(line0 + min(lw, nl - 1)) * ld;
+#pragma unroll
+            for (int k = 0; k < MM; ++k) {
+                const int i = k * ystep + yi0;
+                v[k] = i < N ? s[i] : T(0);
+            }
+        } else {
+            const T *s = src + line0 + min(jcol, nl - 1);
+#pragma unroll
+            for (int k = 0; k < MM; ++k) {
+                const int r = k * rstep + r00;
+                v[k] = r < N ? s[(size_t)r * ld] : T(0);
+            }
+        }
+    };
+    auto put_lines = [&](const T(&v)[MM], T *buf) {
+        if constexpr (DIRY) {
+            T *d = buf + (size_t)lw * Lb + H;
+#pragma unroll
+            for (int k = 0; k < MM; ++k) {
+                const int i = k * ystep + yi0;
+                if (i < N) d[i] = v[k];
+            }
+        } else {
+            T *d = buf + (size_t)jcol * Lb + H;
+#pragma unroll
+            for (int k = 0; k < MM; ++k) {
+                const int r = k * rstep + r00;
+                if (r < N) d[r] = v[k];
+            }
+        }
+    };
+    auto store_lines = [&](T *dst, const T *buf) {
+        T v[MM];
+        if constexpr (DIRY) {
+            if (lw < nl) {
+                const T *b = buf + (size_t)lw * Lb + H;
+#pragma unroll
+                for (int k = 0; k < MM; ++k) {
+                    const int i = k * ystep + yi0;
+                    v[k] = i < N ? b[i] : T(0);
+                }
+                T *d = dst + (size_t)(line0 + lw) * ld;
+#pragma unroll
+                for (int k = 0; k < MM; ++k) {
+                    const int i = k * ystep + yi0;
+                    if (i < N) d[i] = v[k];
+                }
+            }
+        } else {
+            if (jcol < nl) {
+                const T *b = buf + (size_t)jcol * Lb + H;
+#pragma unroll
+                for (int k = 0; k < MM; ++k) {
+                    const int r = k * rstep + r00;
+                    v[k] = r < N ? b[r] : T(0);
+                }
+                T *d = dst + line0 + jcol;
+#pragma unroll
+                for (int k = 0; k < MM; ++k) {
+                    const int r = k * rstep + r00;
+                    if (r < N) d[(size_t)r * ld] = v[k];
+                }
+            }
+        }
+    };
+
+    // the input lines are in flight while the tables are staged
+    T lv[MM];
+    fetch_lines(static_cast<const T *>(job.src), lv);
+
     // LDS: two line buffers [W][Lb] (row r of line l at H + l*Lb + r), then
     // the tables of this job
     T *bufA = reinterpret_cast<T *>(smem);
@@ -264,70 +347,6 @@ __device__ __forceinline__ void wsweep_body(const WSweepParams &prm, const int b
         bufA[(size_t)l * Lb + H + N + r] = T(0);
     }
 
-    // Stage W lines of a field into buffer `buf` (row r of line l at
-    // buf[l*Lb + H + r]) and back.  The full rows are copied in unconditional
-    // batches of 8 per thread (loads issued before their stores); only the
-    // last partial row is guarded.  y-lines: each line is a contiguous run of
-    // N values.  x-lines: rows of W consecutive columns; a workgroup slot past
-    // the last line copies a live column into its own (unused) buffer.
-    const int bd = blockDim.x;
-    auto copy_run_in = [&](const T *src, T *dst, int n) {
-        const int nfull = (n / bd) * bd;
-        int b0 = 0;
-        for (; b0 + 8 * bd <= nfull; b0 += 8 * bd) {
-            T v[8];
-#pragma unroll
-            for (int u = 0; u < 8; ++u) v[u] = src[b0 + u * bd + tid];
-#pragma unroll
-            for (int u = 0; u < 8; ++u) dst[b0 + u * bd + tid] = v[u];
-        }
-        for (; b0 < nfull; b0 += bd) dst[b0 + tid] = src[b0 + tid];
-        if (b0 + tid < n) dst[b0 + tid] = src[b0 + tid];
-    };
-    const int jcol = tid & (W - 1), r00 = tid >> wlog;
-    auto load_lines = [&](const T *src, T *buf) {
-        if constexpr (DIRY) {
-            for (int l = 0; l < nl; ++l)
-                copy_run_in(src + (size_t)(line0 + l) * ld, buf + (size_t)l * Lb + H, N);
-        } else {
-            const T *s = src + line0 + min(jcol, nl - 1);
-            T *d = buf + (size_t)jcol * Lb + H;
-            const int nfull = (N / rstep) * rstep;
-            int b0 = 0;
-            for (; b0 + 8 * rstep <= nfull; b0 += 8 * rstep) {
-                T v[8];
-#pragma unroll
-                for (int u = 0; u < 8; ++u) v[u] = s[(size_t)(b0 + u * rstep + r00) * ld];
-#pragma unroll
-                for (int u = 0; u < 8; ++u) d[b0 + u * rstep + r00] = v[u];
-            }
-            for (; b0 < nfull; b0 += rstep) d[b0 + r00] = s[(size_t)(b0 + r00) * ld];
-            if (b0 + r00 < N) d[b0 + r00] = s[(size_t)(b0 + r00) * ld];
-        }
-    };
-    auto store_lines = [&](T *dst, const T *buf) {
-        if constexpr (DIRY) {
-            for (int l = 0; l < nl; ++l)
-                copy_run_in(buf + (size_t)l * Lb + H, dst + (size_t)(line0 + l) * ld, N);
-        } else {
-            if (jcol < nl) {
-                T *d = dst + line0 + jcol;
-                const T *b = buf + (size_t)jcol * Lb + H;
-                const int nfull = (N / rstep) * rstep;
-                int b0 = 0;
-                for (; b0 + 8 * rstep <= nfull; b0 += 8 * rstep) {
-                    T v[8];
-#pragma unroll
-                    for (int u = 0; u < 8; ++u) v[u] = b[b0 + u * rstep + r00];
-#pragma unroll
-                    for (int u = 0; u < 8; ++u) d[(size_t)(b0 + u * rstep + r00) * ld] = v[u];
-                }
-                for (; b0 < nfull; b0 += rstep) d[(size_t)(b0 + r00) * ld] = b[b0 + r00];
-                if (b0 + r00 < N) d[(size_t)(b0 + r00) * ld] = b[b0 + r00];
-            }
-        }
-    };
-
     // this lane's chunk and table windows
     const int c = part * 64 + lane;
     WinLane<T, P, MM> ln;
@@ -350,7 +369,7 @@ __device__ __forceinline__ void wsweep_body(const WSweepParams &prm, const int b
     T *B = bufB + (size_t)lw * Lb + H;
     const bool live = lw < nl;
 
-    load_lines(static_cast<const T *>(job.src), bufA);
+    put_lines(lv, bufA);
     __syncthreads();
     T x[MM];
 #pragma unroll
@@ -365,6 +384,8 @@ __device__ __forceinline__ void wsweep_body(const WSweepParams &prm, const int b
         __syncthreads();
         if (!*flag) return;   // the same value for every thread of the workgroup
     }
+    // the base state of the increment form is fetched during the solve
+    if (job.base) fetch_lines(static_cast<const T *>(job.base), lv);
     // A: input published; B: free
     if (has0) {
         wsolve_refined<T, P, MM>(x, A, B, tab0, a640, ln, H, Hc);
@@ -372,7 +393,7 @@ __device__ __forceinline__ void wsweep_body(const WSweepParams &prm, const int b
     }
     if (job.base) {
         // increment form: the solve produced x - base; add the base state
-        load_lines(static_cast<const T *>(job.base), bufB);
+        put_lines(lv, bufB);
         __syncthreads();
 #pragma unroll
         for (int k = 0; k < MM; ++k) x[k] += live ? B[ln.r0 + k] : T(0);
