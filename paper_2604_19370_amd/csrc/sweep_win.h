@@ -199,8 +199,9 @@ __device__ __forceinline__ void wsolve_refined(T (&x)[MM], T *bin, T *bout, cons
     }
 }
 
-// One workgroup's work: W lines starting at line blk*W, job `jobi`.
-template <typename T, int P, int MM, bool DIRY>
+// One workgroup's work: W lines starting at line blk*W, job `jobi`.  NB:
+// values of a line a thread loads at once (MM: all of them, see below).
+template <typename T, int P, int MM, bool DIRY, int NB>
 __device__ __forceinline__ void wsweep_body(const WSweepParams &prm, const int blk, const int jobi)
 {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -223,86 +224,104 @@ __device__ __forceinline__ void wsweep_body(const WSweepParams &prm, const int b
 
     // Stage W lines of a field into buffer `buf` (row r of line l at
     // buf[l*Lb + H + r]) and back.  A thread moves at most MM values of a
-    // line (64*WPL*MM >= N): all its loads are issued before the first store,
-    // so a staging costs one memory latency, not one per pass.  y-lines: the
-    // WPL wavefronts of a line copy its contiguous run of N values, 64
-    // consecutive values per wavefront and instruction.  x-lines: rows of W
-    // consecutive columns; a workgroup slot past the last line copies a live
-    // column into its own (unused) buffer.
+    // line (64*WPL*MM >= N), NB at a time, each batch's loads issued before
+    // its stores: a staging costs MM/NB memory latencies.  Where the whole
+    // chunk fits in flight (NB == MM), the input lines load while the tables
+    // are staged and the increment form's base state loads while the line is
+    // solved.  y-lines: the WPL wavefronts of a line copy its contiguous run
+    // of N values, 64 consecutive values per wavefront and instruction.
+    // x-lines: rows of W consecutive columns; a workgroup slot past the last
+    // line copies a live column into its own (unused) buffer.
+    constexpr bool WHOLE = NB >= MM;
     const int jcol = tid & (W - 1), r00 = tid >> wlog;
-    const int yi0 = part * 64 + lane, ystep = 64 * WPL;
-    auto fetch_lines = [&](const T *src, T(&v)[MM]) {
+    const int ystep = 64 * WPL;
+#define IGA_YI0 const int yi0 = part * 64 + (threadIdx.x & 63);
+    auto fetch_lines = [&](const T *src, T *v, int k0) {
         if constexpr (DIRY) {
+            IGA_YI0
             const T *s = src + (size_t)(line0 + min(lw, nl - 1)) * ld;
 #pragma unroll
-            for (int k = 0; k < MM; ++k) {
-                const int i = k * ystep + yi0;
-                v[k] = i < N ? s[i] : T(0);
+            for (int k = 0; k < NB; ++k) {
+                const int i = (k0 + k) * ystep + yi0;
+                v[k] = (k0 + k < MM && i < N) ? s[i] : T(0);
             }
         } else {
             const T *s = src + line0 + min(jcol, nl - 1);
 #pragma unroll
-            for (int k = 0; k < MM; ++k) {
-                const int r = k * rstep + r00;
-                v[k] = r < N ? s[(size_t)r * ld] : T(0);
+            for (int k = 0; k < NB; ++k) {
+                const int r = (k0 + k) * rstep + r00;
+                v[k] = (k0 + k < MM && r < N) ? s[(size_t)r * ld] : T(0);
             }
         }
     };
-    auto put_lines = [&](const T(&v)[MM], T *buf) {
+    auto put_lines = [&](const T *v, T *buf, int k0) {
         if constexpr (DIRY) {
+            IGA_YI0
             T *d = buf + (size_t)lw * Lb + H;
 #pragma unroll
-            for (int k = 0; k < MM; ++k) {
-                const int i = k * ystep + yi0;
-                if (i < N) d[i] = v[k];
+            for (int k = 0; k < NB; ++k) {
+                const int i = (k0 + k) * ystep + yi0;
+                if (k0 + k < MM && i < N) d[i] = v[k];
             }
         } else {
             T *d = buf + (size_t)jcol * Lb + H;
 #pragma unroll
-            for (int k = 0; k < MM; ++k) {
-                const int r = k * rstep + r00;
-                if (r < N) d[r] = v[k];
+            for (int k = 0; k < NB; ++k) {
+                const int r = (k0 + k) * rstep + r00;
+                if (k0 + k < MM && r < N) d[r] = v[k];
             }
         }
     };
+    auto load_lines = [&](const T *src, T *buf) {
+#pragma unroll 1
+        for (int k0 = 0; k0 < MM; k0 += NB) {
+            T v[NB];
+            fetch_lines(src, v, k0);
+            put_lines(v, buf, k0);
+        }
+    };
     auto store_lines = [&](T *dst, const T *buf) {
-        T v[MM];
-        if constexpr (DIRY) {
-            if (lw < nl) {
-                const T *b = buf + (size_t)lw * Lb + H;
+#pragma unroll 1
+        for (int k0 = 0; k0 < MM; k0 += NB) {
+            T v[NB];
+            if constexpr (DIRY) {
+                if (lw < nl) {
+                    IGA_YI0
+                    const T *b = buf + (size_t)lw * Lb + H;
 #pragma unroll
-                for (int k = 0; k < MM; ++k) {
-                    const int i = k * ystep + yi0;
-                    v[k] = i < N ? b[i] : T(0);
+                    for (int k = 0; k < NB; ++k) {
+                        const int i = (k0 + k) * ystep + yi0;
+                        v[k] = (k0 + k < MM && i < N) ? b[i] : T(0);
+                    }
+                    T *d = dst + (size_t)(line0 + lw) * ld;
+#pragma unroll
+                    for (int k = 0; k < NB; ++k) {
+                        const int i = (k0 + k) * ystep + yi0;
+                        if (k0 + k < MM && i < N) d[i] = v[k];
+                    }
                 }
-                T *d = dst + (size_t)(line0 + lw) * ld;
+            } else {
+                if (jcol < nl) {
+                    const T *b = buf + (size_t)jcol * Lb + H;
 #pragma unroll
-                for (int k = 0; k < MM; ++k) {
-                    const int i = k * ystep + yi0;
-                    if (i < N) d[i] = v[k];
-                }
-            }
-        } else {
-            if (jcol < nl) {
-                const T *b = buf + (size_t)jcol * Lb + H;
+                    for (int k = 0; k < NB; ++k) {
+                        const int r = (k0 + k) * rstep + r00;
+                        v[k] = (k0 + k < MM && r < N) ? b[r] : T(0);
+                    }
+                    T *d = dst + line0 + jcol;
 #pragma unroll
-                for (int k = 0; k < MM; ++k) {
-                    const int r = k * rstep + r00;
-                    v[k] = r < N ? b[r] : T(0);
-                }
-                T *d = dst + line0 + jcol;
-#pragma unroll
-                for (int k = 0; k < MM; ++k) {
-                    const int r = k * rstep + r00;
-                    if (r < N) d[(size_t)r * ld] = v[k];
+                    for (int k = 0; k < NB; ++k) {
+                        const int r = (k0 + k) * rstep + r00;
+                        if (k0 + k < MM && r < N) d[(size_t)r * ld] = v[k];
+                    }
                 }
             }
         }
     };
 
-    // the input lines are in flight while the tables are staged
-    T lv[MM];
-    fetch_lines(static_cast<const T *>(job.src), lv);
+#undef IGA_YI0
+    T lv[NB];
+    if (WHOLE) fetch_lines(static_cast<const T *>(job.src), lv, 0);
 
     // LDS: two line buffers [W][Lb] (row r of line l at H + l*Lb + r), then
     // the tables of this job
@@ -369,7 +388,10 @@ __device__ __forceinline__ void wsweep_body(const WSweepParams &prm, const int b
     T *B = bufB + (size_t)lw * Lb + H;
     const bool live = lw < nl;
 
-    put_lines(lv, bufA);
+    if (WHOLE)
+        put_lines(lv, bufA, 0);
+    else
+        load_lines(static_cast<const T *>(job.src), bufA);
     __syncthreads();
     T x[MM];
 #pragma unroll
@@ -384,8 +406,7 @@ __device__ __forceinline__ void wsweep_body(const WSweepParams &prm, const int b
         __syncthreads();
         if (!*flag) return;   // the same value for every thread of the workgroup
     }
-    // the base state of the increment form is fetched during the solve
-    if (job.base) fetch_lines(static_cast<const T *>(job.base), lv);
+    if (WHOLE && job.base) fetch_lines(static_cast<const T *>(job.base), lv, 0);
     // A: input published; B: free
     if (has0) {
         wsolve_refined<T, P, MM>(x, A, B, tab0, a640, ln, H, Hc);
@@ -393,7 +414,10 @@ __device__ __forceinline__ void wsweep_body(const WSweepParams &prm, const int b
     }
     if (job.base) {
         // increment form: the solve produced x - base; add the base state
-        put_lines(lv, bufB);
+        if (WHOLE)
+            put_lines(lv, bufB, 0);
+        else
+            load_lines(static_cast<const T *>(job.base), bufB);
         __syncthreads();
 #pragma unroll
         for (int k = 0; k < MM; ++k) x[k] += live ? B[ln.r0 + k] : T(0);
@@ -447,10 +471,23 @@ template <typename T, int P, int MM> constexpr int wsweep_max_threads()
     return (MM >= 25 || (sizeof(T) == 8 && MM >= 17)) ? 512 : 1024;
 }
 
+// Values in flight per thread when lines are staged: the whole chunk where
+// the registers hold it without spilling (checked per variant against the
+// compiler's resource report), else batches of four.  The batched-launch
+// form carries more state and gets the smaller budget.
+template <typename T, int P, int MM, bool BATCH> constexpr int wsweep_nb()
+{
+    if (wsweep_max_threads<T, P, MM>() == 512) return MM;   // 256 registers
+    const int bytes = MM * (int)sizeof(T);
+    const int fits = BATCH ? 36 : (P <= 2 ? 68 : 36);
+    return bytes <= fits ? MM : 4;
+}
+
 template <typename T, int P, int MM, bool DIRY>
 __global__ __launch_bounds__((wsweep_max_threads<T, P, MM>())) void k_wsweep(WSweepParams prm)
 {
-    wsweep_body<T, P, MM, DIRY>(prm, xcd_remap(blockIdx.x, gridDim.x), blockIdx.y);
+    wsweep_body<T, P, MM, DIRY, wsweep_nb<T, P, MM, false>()>(prm, xcd_remap(blockIdx.x, gridDim.x),
+                                                              blockIdx.y);
 }
 
 template <typename T, int P, int MM, bool DIRY>
@@ -461,7 +498,7 @@ __global__ __launch_bounds__((wsweep_max_threads<T, P, MM>())) void k_wsweep_bat
     if (bi.x < 0) return;
     const WSweepParams &prm = prms[bi.x];
     if ((int)blockIdx.y >= prm.njobs) return;
-    wsweep_body<T, P, MM, DIRY>(prm, bi.y, blockIdx.y);
+    wsweep_body<T, P, MM, DIRY, wsweep_nb<T, P, MM, true>()>(prm, bi.y, blockIdx.y);
 }
 
 using WSweepFn = void (*)(WSweepParams);
