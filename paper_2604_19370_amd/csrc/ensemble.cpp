@@ -321,25 +321,36 @@ iga_status iga_ensemble_autotune(iga_ensemble *ens, void *const *T, void *const 
         }
         if ((st = iga_ensemble_set_assembly_rows(ens, best))) return st;
     }
-    // line solves: lines per workgroup x wavefronts per line, timed on jobs
-    // shaped like the step's that read and write the scratch fields only
+    // line solves: lines per workgroup x wavefronts per line (or rows per
+    // lane), timed on both of the step's launches of the direction with the
+    // step's own jobs (fused Crank-Nicolson solves, base states, zero skips),
+    // every state field replaced by a scratch buffer of the member: the
+    // caller's fields are not written
     for (int dir = 0; dir < 2; ++dir) {
-        std::vector<std::vector<SweepJob>> jobs(n);
+        std::vector<iga_plan *> second;
+        std::vector<std::vector<SweepJob>> ja(n), jb;
         for (size_t m = 0; m < n; ++m) {
-            const iga_plan *pl = ens->plans[m];
-            void *R = pl->scratch_r.ptr, *RF = pl->scratch_rf.ptr;
-            if (dir == 0)
-                jobs[m] = {{R, R, OP_AX, -1, -1, nullptr, 0}, {RF, RF, OP_MX, -1, -1, nullptr, 0}};
-            else
-                jobs[m] = {{R, R, OP_MY, -1, -1, pl->delta ? RF : nullptr, 0},
-                           {RF, RF, OP_MY, -1, -1, pl->delta ? R : nullptr, 0}};
+            iga_plan *pl = ens->plans[m];
+            const bool r2 = pl->scratch_r2.ptr != nullptr;   // FP32 plans
+            StepPhases sp;
+            step_phases(pl, r2 ? pl->scratch_r2.ptr : pl->scratch_r.ptr,
+                        r2 ? pl->scratch_rf2.ptr : pl->scratch_rf.ptr, sp);
+            ja[m] = dir == 0 ? sp.x1 : sp.y1;
+            if (sp.two) {
+                second.push_back(pl);
+                jb.push_back(dir == 0 ? sp.x2 : sp.y2);
+            }
         }
         int best_l = 0, best_w = 0, best_win = 0;
         float best_ms = 1e30f;
         auto consider = [&](int lines, int w, int win) {
-            std::vector<BatchLaunch> bl;
-            if (build_sweep_batch(ens->plans, dir, jobs, bl) != IGA_OK) return;
-            float ms = time_launches(s, reps, [&] { return launch_all(bl, s); });
+            std::vector<BatchLaunch> bla, blb;
+            if (build_sweep_batch(ens->plans, dir, ja, bla) != IGA_OK) return;
+            if (!second.empty() && build_sweep_batch(second, dir, jb, blb) != IGA_OK) return;
+            float ms = time_launches(s, reps, [&] {
+                iga_status e = launch_all(bla, s);
+                return e ? e : launch_all(blb, s);
+            });
             if (ms >= 0 && ms < best_ms) {
                 best_ms = ms;
                 best_l = lines;
