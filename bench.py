@@ -342,7 +342,7 @@ def main():
         print(json.dumps({"kernel_us": {k: round(v * 1e6, 2) for k, v in kt.items()},
                           "schedules": [dict(pl.schedule(0), **pl.solver(0)),
                                         dict(pl.schedule(1), **pl.solver(1)),
-                                        {"assembly_rows": pl.assembly_rows}],
+                                        {"assembly_rows": pl.assembly_rows, "assembly_stacked": pl.assembly_stacked}],
                           "copy_bytes": 4 * sc.ndof}), flush=True)
         pl.close()
         return
@@ -364,7 +364,7 @@ def main():
         res[prec] = dict(wall=wall, ev=ev, dofs=sc.ndof * args.steps / wall,
                          sched=[dict(pl.schedule(0), **pl.solver(0)),
                                 dict(pl.schedule(1), **pl.solver(1)),
-                                {"assembly_rows": pl.assembly_rows}])
+                                {"assembly_rows": pl.assembly_rows, "assembly_stacked": pl.assembly_stacked}])
         ktimes[prec] = kernel_times(pl, sc, args.kernel_reps, torch)
         pl.close()
 

@@ -242,9 +242,19 @@ iga_status iga_plan_set_column_schedule(iga_plan *plan, int32_t rows_per_chunk);
  * factorisation).  Either pointer may be NULL. */
 iga_status iga_plan_solver(const iga_plan *plan, int32_t dir, int32_t *windowed, int32_t *warmup);
 
-/* Assembly schedule: element rows marched per wavefront (>= 1). */
+/* Assembly schedule: dof rows per wavefront tile, at least p + 1
+ * (IGA_EINVAL below).  A workgroup takes four consecutive tiles of a strip.
+ * Stacked (1): only its first tile, p rows shorter than the others,
+ * re-evaluates the p elements above it; the rows where two of its tiles meet
+ * are summed in two parts through LDS (deterministic).  Unstacked (0): every
+ * tile re-evaluates its own p halo elements, and the wavefronts never wait
+ * for each other.  Defaults: 16 rows (32 from 2048 dof rows), stacked for
+ * FP32 plans of degree <= 2; iga_autotune times both kinds.  stacked must be
+ * 0 or 1 (IGA_EINVAL). */
 iga_status iga_plan_set_assembly_rows(iga_plan *plan, int32_t rows);
 int32_t iga_plan_assembly_rows(const iga_plan *plan);
+iga_status iga_plan_set_assembly_stacking(iga_plan *plan, int32_t stacked);
+int32_t iga_plan_assembly_stacking(const iga_plan *plan);
 
 /* Autotuner: times, with HIP events on `stream`, the assembly of the first
  * substep for several element-row tiles and the line solves of each direction
@@ -309,6 +319,8 @@ iga_status iga_ensemble_set_schedule(iga_ensemble *ens, int32_t dir, int32_t lin
 iga_status iga_ensemble_set_window_schedule(iga_ensemble *ens, int32_t dir, int32_t lines,
                                             int32_t rows_per_lane);
 iga_status iga_ensemble_set_assembly_rows(iga_ensemble *ens, int32_t rows);
+/* As iga_plan_set_assembly_stacking, on every member. */
+iga_status iga_ensemble_set_assembly_stacking(iga_ensemble *ens, int32_t stacked);
 
 /* Autotuner of the batched launches: element-row tiles of the assembly, and
  * (lines, waves per line) per direction, timed with HIP events on `stream` on

@@ -191,6 +191,7 @@ iga_status iga_plan_create(const iga_plan_desc *desc, iga_plan **out)
             return st;
         }
         pl->asm_rows = pl->Nx >= 2048 ? 32 : 16;
+        pl->asm_stack = pl->fp32 && pl->P <= 2;
     } catch (const std::bad_alloc &) {
         delete pl;
         return fail(IGA_ENOMEM, "host allocation failed");
@@ -433,13 +434,24 @@ iga_status iga_plan_solver(const iga_plan *plan, int32_t dir, int32_t *windowed,
 iga_status iga_plan_set_assembly_rows(iga_plan *plan, int32_t rows)
 {
     if (!plan) return fail(IGA_EINVAL, "plan is NULL");
-    if (rows < 1) return fail(IGA_EINVAL, "rows must be >= 1");
+    if (rows < plan->P + 1) return fail(IGA_EINVAL, "rows must be at least p + 1");
     plan->asm_rows = rows;
     plan->graph.reset();
     return IGA_OK;
 }
 
 int32_t iga_plan_assembly_rows(const iga_plan *plan) { return plan ? plan->asm_rows : 0; }
+
+iga_status iga_plan_set_assembly_stacking(iga_plan *plan, int32_t stacked)
+{
+    if (!plan) return fail(IGA_EINVAL, "plan is NULL");
+    if (stacked != 0 && stacked != 1) return fail(IGA_EINVAL, "stacked must be 0 or 1");
+    plan->asm_stack = stacked;
+    plan->graph.reset();
+    return IGA_OK;
+}
+
+int32_t iga_plan_assembly_stacking(const iga_plan *plan) { return plan ? plan->asm_stack : 0; }
 
 iga_status iga_autotune(iga_plan *plan, const void *T, const void *fuel, int32_t reps, void *stream)
 {
@@ -455,15 +467,23 @@ iga_status iga_autotune(iga_plan *plan, const void *T, const void *fuel, int32_t
     void *out2 = out.as<char>() + plan->ndof * plan->wsize;
     // assembly: element rows marched per wavefront
     {
-        int best = plan->asm_rows;
+        int best = plan->asm_rows, best_stack = plan->asm_stack;
         float best_ms = 1e30f;
-        for (int rows : ASSEMBLY_ROW_CANDIDATES) {
-            if (rows > plan->Nx && rows != 4) continue;
-            plan->asm_rows = rows;
-            float ms = time_launches(s, reps, [&] { return launch_assemble(plan, 0, T, fuel, R, RF, s); });
-            if (ms >= 0 && ms < best_ms) { best_ms = ms; best = rows; }
-        }
+        for (int stack : {0, 1})
+            for (int rows : ASSEMBLY_ROW_CANDIDATES) {
+                if ((rows > plan->Nx && rows != 4) || rows < plan->P + 1) continue;
+                plan->asm_rows = rows;
+                plan->asm_stack = stack;
+                float ms =
+                    time_launches(s, reps, [&] { return launch_assemble(plan, 0, T, fuel, R, RF, s); });
+                if (ms >= 0 && ms < best_ms) {
+                    best_ms = ms;
+                    best = rows;
+                    best_stack = stack;
+                }
+            }
         plan->asm_rows = best;
+        plan->asm_stack = best_stack;
         if ((st = launch_assemble(plan, 0, T, fuel, R, RF, s))) return st;
     }
     // line solves: lines per workgroup, timed on the step's own jobs

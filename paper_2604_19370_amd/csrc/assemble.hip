@@ -27,8 +27,12 @@
 // registers, evaluates the pointwise terms at the (p+1)^2 points and
 // accumulates the x half of the test-function contraction into per-row
 // accumulators.  When a dof row is complete its y contraction is gathered from
-// the p neighbouring lanes and stored.  Every dof is summed by exactly one lane
-// in a fixed order: no atomics, deterministic.
+// the p neighbouring lanes and stored.  A workgroup's four wavefronts take
+// four consecutive tiles of one strip; the p dof rows where two of its tiles
+// meet are summed in two parts (the upper tile's elements, then the lower
+// one's) that meet in LDS, so only the first tile re-evaluates the p elements
+// above it.  Every dof is summed by one lane, or two parts by two fixed
+// lanes, in a fixed order: no atomics, deterministic.
 //
 // The marching loop is unrolled by p+1, so the rolling windows (coefficient
 // rows, accumulators, pending loads) are renamed, not copied.  The x
@@ -58,7 +62,9 @@ template <typename T> struct AsmParams {
     T cx, cy, bca;      // bca = beta c_adv
     T t_ig, t_skip, fthr, t_act;
     int fuel_all;       // fuel right-hand side nonzero without ignition (direct form)
-    int nel_x, nel_y, Nx, Ny, rows, nstrips, ntiles;
+    int nel_x, nel_y, Nx, Ny, rows, nstrips, ntiles, ngroups;   // rows: dof rows per tile
+    int stack;   // tiles of a workgroup share halos (else each evaluates its own);
+                 // the kernels are compiled for one or the other
     // source samples src[(ex*Q + qx) * nel_y*Q + ey*Q + qy] (forced variant),
     // weighted by src_w[qx] = beta * x weight
     const T *src;
@@ -69,13 +75,21 @@ template <int N> struct Ic {
     static constexpr int value = N;
 };
 
-// The work of wavefront gw (strip gw mod nstrips, tile gw / nstrips).
+// The work of one wavefront: dof rows [X0, X1) of strip `strip` (and the
+// elements of those rows).
+//   halo: also evaluate the p elements above the tile, so that its first p
+//         dof rows are complete (the first tile of a workgroup);
+//   hold: those p rows get the contributions of the tile's own elements only
+//         and go to hd[2][P][64] (T, fuel) for the workgroup to finish;
+//   tail: march p more steps without elements, and put the contributions of
+//         the tile's last elements to the p rows below it into tl[2][P][64].
 template <typename T, int P, bool FUEL, bool SRC = false>
-__device__ __forceinline__ void assemble_body(const AsmParams<T> &a, const int gw)
+__device__ __forceinline__ void assemble_body(const AsmParams<T> &a, const int strip, const int X0,
+                                              const int X1, const bool halo, const bool hold, const bool tail,
+                                              T *__restrict__ hd, T *__restrict__ tl)
 {
     constexpr int Q = P + 1;
     const int lane = threadIdx.x & 63;
-    const int strip = gw % a.nstrips, tile = gw / a.nstrips;
     const int J0 = strip * (64 - P);
     const int ey = J0 - P + lane;
     const bool eyok = ey >= 0 && ey < a.nel_y;
@@ -147,9 +161,8 @@ __device__ __forceinline__ void assemble_body(const AsmParams<T> &a, const int g
         }
     };
 
-    const int X0 = tile * a.rows;
-    const int X1 = min(X0 + a.rows, a.Nx);
-    const int K = X1 - (X0 - P);   // marching steps: element rows X0-P .. X1-1
+    const int E0 = halo ? X0 - P : X0;       // first element row marched
+    const int K = X1 - E0 + (tail ? P : 0);   // marching steps
     // rings indexed by (step + i) mod Q
     T tv[Q][Q], td[Q][Q], tf[Q][Q], rmx[Q];
     T acc0[Q][Q], acc1[Q][Q], accf[Q][Q];
@@ -158,25 +171,25 @@ __device__ __forceinline__ void assemble_body(const AsmParams<T> &a, const int g
     for (int i = 0; i < Q; ++i)
 #pragma unroll
         for (int q = 0; q < Q; ++q) acc0[i][q] = acc1[i][q] = accf[i][q] = T(0);
-    // window rows X0-P .. X0-1 in slots 0 .. P-1
+    // window rows E0 .. E0+P-1 in slots 0 .. P-1
 #pragma unroll
     for (int s = 0; s < P; ++s) {
         T c0, c1, f0, f1;
-        fetch(X0 - P + s, c0, c1, f0, f1);
+        fetch(E0 + s, c0, c1, f0, f1);
         ytransform(c0, c1, f0, f1, tv[s], td[s], tf[s], rmx[s]);
     }
-    // pending loads: step k consumes row X0 + k from slot k mod Q
+    // pending loads: step k consumes row E0 + P + k from slot k mod Q
 #pragma unroll
-    for (int s = 0; s < Q; ++s) fetch(X0 + s, pc0[s], pc1[s], pf0[s], pf1[s]);
+    for (int s = 0; s < Q; ++s) fetch(E0 + P + s, pc0[s], pc1[s], pf0[s], pf1[s]);
 
     const T t_skip = a.t_skip;
     auto step = [&](auto phase, int k) {
         constexpr int ph = decltype(phase)::value;
         constexpr int snew = (ph + P) % Q;   // slot of the new coefficient row / dof row ex+P
-        const int ex = X0 - P + k;
+        const int ex = E0 + k;
         ytransform(pc0[ph], pc1[ph], pf0[ph], pf1[ph], tv[snew], td[snew], tf[snew], rmx[snew]);
         fetch(ex + P + Q, pc0[ph], pc1[ph], pf0[ph], pf1[ph]);
-        if (ex >= 0 && ex < a.nel_x) {
+        if (ex >= 0 && ex < a.nel_x && ex < X1) {
             const int e2 = (ex >= P && ex < a.nel_x - P) ? P : ex;   // interior tables coincide
             const T *bxe = a.bx + (size_t)e2 * 2 * Q * Q;
             T bxv[Q][Q], bxd[Q][Q], kyw[Q];
@@ -297,7 +310,14 @@ __device__ __forceinline__ void assemble_body(const AsmParams<T> &a, const int g
                 r += lane_behind<3>(pb[3]);
                 if (FUEL) rf += lane_behind<3>(pf[3]);
             }
-            if (lane >= P && colA < Ny) {
+            const int hi = ex - X0, ti = ex - X1;
+            if (hold && hi < P) {
+                hd[hi * 64 + lane] = r;
+                if (FUEL) hd[(P + hi) * 64 + lane] = rf;
+            } else if (ti >= 0) {
+                tl[ti * 64 + lane] = r;
+                if (FUEL) tl[(P + ti) * 64 + lane] = rf;
+            } else if (lane >= P && colA < Ny) {
                 a.R[(size_t)ex * Ny + colA] = r;
                 if (FUEL) a.RF[(size_t)ex * Ny + colA] = rf;
             }
@@ -325,6 +345,61 @@ __device__ __forceinline__ void assemble_body(const AsmParams<T> &a, const int g
     }
 }
 
+// The work of workgroup `grp`: four wavefronts on four consecutive tiles of
+// dof rows of one strip.  Stacked (a.stack): only the first evaluates the p
+// elements above its tile (the halo); each later wavefront leaves its first
+// p dof rows with its own elements' contributions in LDS, its predecessor
+// adds the contributions of its last elements to the same rows, and after
+// the barrier the later wavefront stores predecessor + own, in that order
+// (deterministic, no atomics).  The first tile is p rows shorter than the
+// others, so that the four wavefronts march the same number of elements; a
+// group covers 4 rows - p dof rows, and a tile shorter than p rows evaluates
+// its own halo.  Unstacked: the four wavefronts take neighbouring strips of
+// one tile row, every tile evaluates its own halo and no wavefront waits for
+// another (better where few wavefronts fit per SIMD).
+template <typename T, int P, bool FUEL, bool SRC, bool STK>
+__device__ __forceinline__ void assemble_group(const AsmParams<T> &a, const int grp)
+{
+    constexpr int G = 4;   // wavefronts per workgroup
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    if constexpr (!STK) {
+        // independent wavefronts: four neighbouring strips of one tile row
+        const int gw = grp * G + w;
+        if (gw >= a.nstrips * a.ntiles) return;
+        const int X0 = (gw / a.nstrips) * a.rows;
+        assemble_body<T, P, FUEL, SRC>(a, gw % a.nstrips, X0, min(X0 + a.rows, a.Nx), X0 > 0, false,
+                                       false, nullptr, nullptr);
+    } else {
+        __shared__ T part[2][G][2 * P * 64];   // [head, tail][wavefront][(T, fuel) x row x lane]
+        const int strip = grp % a.nstrips;
+        const int base = (grp / a.nstrips) * (G * a.rows - P);
+        // dof rows of the tile of wavefront ww (the first is p rows shorter)
+        auto first = [&](int ww) { return min(base + (ww == 0 ? 0 : ww * a.rows - P), a.Nx); };
+        auto last = [&](int ww) { return min(base + (ww + 1) * a.rows - P, a.Nx); };
+        auto holds = [&](int ww) { return ww > 0 && ww < G && first(ww) > 0 && last(ww) - first(ww) >= P; };
+        const int X0 = first(w), X1 = last(w);
+        const bool live = X1 > X0;
+        const bool hold = holds(w);
+        const bool halo = live && X0 > 0 && !hold;
+        const bool tail = live && holds(w + 1);
+        if (live) assemble_body<T, P, FUEL, SRC>(a, strip, X0, X1, halo, hold, tail, part[0][w], part[1][w]);
+        __syncthreads();
+        if (hold) {
+            const int lane = threadIdx.x & 63;
+            const int colA = strip * (64 - P) - P + lane;
+            if (lane >= P && colA < a.Ny) {
+#pragma unroll
+                for (int i = 0; i < P; ++i) {
+                    const size_t o = (size_t)(X0 + i) * a.Ny + colA;
+                    a.R[o] = part[1][w - 1][i * 64 + lane] + part[0][w][i * 64 + lane];
+                    if (FUEL)
+                        a.RF[o] = part[1][w - 1][(P + i) * 64 + lane] + part[0][w][(P + i) * 64 + lane];
+                }
+            }
+        }
+    }
+}
+
 // Occupancy target: float cubic kernels sit a few registers above the 256
 // that allow two wavefronts per SIMD; asking for two costs a couple of
 // spilled registers and doubles the wavefronts in flight.  Elsewhere the
@@ -333,25 +408,22 @@ template <typename T, int P> struct AsmWaves {
     static constexpr int value = (sizeof(T) == 4 && P == 3) ? 2 : 1;
 };
 
-template <typename T, int P, bool FUEL, bool SRC>
+template <typename T, int P, bool FUEL, bool SRC, bool STK>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(AsmWaves<T, P>::value)))
 void k_assemble(AsmParams<T> a)
 {
-    const int gw = blockIdx.x * (blockDim.x >> 6) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    if (gw >= a.nstrips * a.ntiles) return;
-    assemble_body<T, P, FUEL, SRC>(a, gw);
+    assemble_group<T, P, FUEL, SRC, STK>(a, blockIdx.x);
 }
 
-// Batched launch over the members of an ensemble: wavefront w does wavefront
-// info[w].y of member info[w].x (x < 0: no work).
-template <typename T, int P, bool FUEL>
+// Batched launch over the members of an ensemble: workgroup b does workgroup
+// info[b].y of member info[b].x (x < 0: no work).
+template <typename T, int P, bool FUEL, bool STK>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(AsmWaves<T, P>::value)))
 void k_assemble_batch(const AsmParams<T> *__restrict__ prms, const int2 *__restrict__ info)
 {
-    const int gw = blockIdx.x * (blockDim.x >> 6) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int2 wi = info[gw];
-    if (wi.x < 0) return;
-    assemble_body<T, P, FUEL>(prms[wi.x], wi.y);
+    const int2 wi = info[blockIdx.x];
+    if (wi.x < 0) return;   // the whole workgroup
+    assemble_group<T, P, FUEL, false, STK>(prms[wi.x], wi.y);
 }
 
 template <typename T>
@@ -434,7 +506,16 @@ static void make_params(const iga_plan *pl, int substep, const void *S, const vo
     a.Ny = pl->Ny;
     a.rows = pl->asm_rows;
     a.nstrips = (pl->Ny + (64 - P) - 1) / (64 - P);
+    a.stack = pl->asm_stack;
     a.ntiles = (pl->Nx + a.rows - 1) / a.rows;
+    a.ngroups = (pl->Nx + 4 * a.rows - P - 1) / (4 * a.rows - P);
+}
+
+// workgroups of one assembly launch: four tiles of one strip each (stacked),
+// or four wavefronts on neighbouring strips of a tile row
+template <typename T> static int asm_groups(const AsmParams<T> &a)
+{
+    return a.stack ? a.nstrips * a.ngroups : (a.nstrips * a.ntiles + 3) / 4;
 }
 
 template <typename T>
@@ -444,15 +525,21 @@ static iga_status launch_t(const iga_plan *pl, int substep, const void *S, const
     AsmParams<T> a;
     make_params<T>(pl, substep, S, F, R, RF, a, src);
     const int P = pl->P;
-    const int waves = a.nstrips * a.ntiles;
-    const int blocks = (waves + 3) / 4;
+    const int blocks = asm_groups(a);
     const bool fuel = RF != nullptr;
-#define IGA_ASM(P_, FU_)                                                                          \
-    do {                                                                                          \
-        if (src)                                                                                  \
-            hipLaunchKernelGGL((k_assemble<T, P_, FU_, true>), dim3(blocks), dim3(256), 0, s, a); \
-        else                                                                                      \
-            hipLaunchKernelGGL((k_assemble<T, P_, FU_, false>), dim3(blocks), dim3(256), 0, s, a); \
+#define IGA_ASM_S(P_, FU_, SR_)                                                                     \
+    do {                                                                                            \
+        if (a.stack)                                                                                \
+            hipLaunchKernelGGL((k_assemble<T, P_, FU_, SR_, true>), dim3(blocks), dim3(256), 0, s, a); \
+        else                                                                                        \
+            hipLaunchKernelGGL((k_assemble<T, P_, FU_, SR_, false>), dim3(blocks), dim3(256), 0, s, a); \
+    } while (0)
+#define IGA_ASM(P_, FU_)              \
+    do {                              \
+        if (src)                      \
+            IGA_ASM_S(P_, FU_, true); \
+        else                          \
+            IGA_ASM_S(P_, FU_, false); \
     } while (0)
     if (P == 1) {
         if (fuel) IGA_ASM(1, true);
@@ -467,6 +554,7 @@ static iga_status launch_t(const iga_plan *pl, int substep, const void *S, const
         return fail(IGA_EUNSUPPORTED, "degree not compiled");
     }
 #undef IGA_ASM
+#undef IGA_ASM_S
     IGA_HIP(hipGetLastError());
     return IGA_OK;
 }
@@ -487,16 +575,20 @@ static iga_status batch_t(const std::vector<iga_plan *> &pls, const std::vector<
     std::vector<AsmParams<T>> prms(pls.size());
     std::vector<int2> info;
     for (size_t m = 0; m < pls.size(); ++m) {
-        if (pls[m]->P != P || pls[m]->fp32 != pls[0]->fp32 || (args[m].RF != nullptr) != fuel)
-            return fail(IGA_EINVAL, "assembly batch: members differ in degree, precision or fuel");
+        if (pls[m]->P != P || pls[m]->fp32 != pls[0]->fp32 || (args[m].RF != nullptr) != fuel ||
+            pls[m]->asm_stack != pls[0]->asm_stack)
+            return fail(IGA_EINVAL,
+                        "assembly batch: members differ in degree, precision, fuel or tile stacking");
         make_params<T>(pls[m], args[m].substep, args[m].T, args[m].fuel, args[m].R, args[m].RF,
                        prms[m]);
-        const int waves = prms[m].nstrips * prms[m].ntiles;
-        for (int w = 0; w < waves; ++w) info.push_back(int2{(int)m, w});
+        const int groups = asm_groups(prms[m]);
+        for (int g = 0; g < groups; ++g) info.push_back(int2{(int)m, g});
     }
-    while (info.size() % 4) info.push_back(int2{-1, 0});
     const void *fn = nullptr;
-#define IGA_ASMB(P_, FU_) fn = reinterpret_cast<const void *>(k_assemble_batch<T, P_, FU_>)
+    const bool stk = pls[0]->asm_stack != 0;
+#define IGA_ASMB(P_, FU_)                                                                    \
+    fn = stk ? reinterpret_cast<const void *>(k_assemble_batch<T, P_, FU_, true>)           \
+             : reinterpret_cast<const void *>(k_assemble_batch<T, P_, FU_, false>)
     if (P == 1) {
         if (fuel) IGA_ASMB(1, true);
         else IGA_ASMB(1, false);
@@ -511,7 +603,7 @@ static iga_status batch_t(const std::vector<iga_plan *> &pls, const std::vector<
     }
 #undef IGA_ASMB
     out.fn = fn;
-    out.nblk = (int)(info.size() / 4);
+    out.nblk = (int)info.size();
     out.njobs = 1;
     out.block = 256;
     out.lds = 0;

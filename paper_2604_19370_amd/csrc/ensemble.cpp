@@ -292,8 +292,17 @@ iga_status iga_ensemble_set_window_schedule(iga_ensemble *ens, int32_t dir, int3
 iga_status iga_ensemble_set_assembly_rows(iga_ensemble *ens, int32_t rows)
 {
     if (!ens) return fail(IGA_EINVAL, "ensemble is NULL");
-    if (rows < 1) return fail(IGA_EINVAL, "rows must be >= 1");
+    if (rows < ens->P + 1) return fail(IGA_EINVAL, "rows must be at least p + 1");
     for (iga_plan *pl : ens->plans) pl->asm_rows = rows;
+    ens->unbind();
+    return IGA_OK;
+}
+
+iga_status iga_ensemble_set_assembly_stacking(iga_ensemble *ens, int32_t stacked)
+{
+    if (!ens) return fail(IGA_EINVAL, "ensemble is NULL");
+    if (stacked != 0 && stacked != 1) return fail(IGA_EINVAL, "stacked must be 0 or 1");
+    for (iga_plan *pl : ens->plans) pl->asm_stack = stacked;
     ens->unbind();
     return IGA_OK;
 }
@@ -309,17 +318,24 @@ iga_status iga_ensemble_autotune(iga_ensemble *ens, void *const *T, void *const 
     const size_t n = ens->plans.size();
     // assembly rows, timed on the first assembly (it writes scratch only)
     {
-        int best = ens->plans[0]->asm_rows;
+        int best = ens->plans[0]->asm_rows, best_stack = ens->plans[0]->asm_stack;
         float best_ms = 1e30f;
-        for (int rows : ASSEMBLY_ROW_CANDIDATES) {
-            if ((st = iga_ensemble_set_assembly_rows(ens, rows)) || (st = bind(ens, T, fuel))) return st;
-            float ms = time_launches(s, reps, [&] { return launch_batch(ens->a1, s); });
-            if (ms >= 0 && ms < best_ms) {
-                best_ms = ms;
-                best = rows;
+        for (int stack : {0, 1})
+            for (int rows : ASSEMBLY_ROW_CANDIDATES) {
+                if (rows < ens->P + 1) continue;
+                if ((st = iga_ensemble_set_assembly_rows(ens, rows)) ||
+                    (st = iga_ensemble_set_assembly_stacking(ens, stack)) || (st = bind(ens, T, fuel)))
+                    return st;
+                float ms = time_launches(s, reps, [&] { return launch_batch(ens->a1, s); });
+                if (ms >= 0 && ms < best_ms) {
+                    best_ms = ms;
+                    best = rows;
+                    best_stack = stack;
+                }
             }
-        }
-        if ((st = iga_ensemble_set_assembly_rows(ens, best))) return st;
+        if ((st = iga_ensemble_set_assembly_rows(ens, best)) ||
+            (st = iga_ensemble_set_assembly_stacking(ens, best_stack)))
+            return st;
     }
     // line solves: lines per workgroup x wavefronts per line (or rows per
     // lane), timed on both of the step's launches of the direction with the

@@ -165,6 +165,7 @@ struct iga_plan {
     std::vector<double> cn_band[iga::NBANDS];  // explicit CN operators (B, or B - A)
     iga::Schedule sched[2];
     int asm_rows = 16;
+    int asm_stack = 0;   // assembly tiles share halos within four-tile workgroups
 
     // device LU (input bands and factors, double)
     iga::DevBuf op_a64[iga::NOPS], op_lf64[iga::NOPS], op_uf64[iga::NOPS];

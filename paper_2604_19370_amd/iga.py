@@ -28,7 +28,9 @@ EXPORTED = ("iga_default_coeffs", "iga_plan_create", "iga_plan_destroy", "iga_pl
             "iga_ensemble_size", "iga_ensemble_launches", "iga_ensemble_step", "iga_ensemble_run",
             "iga_ensemble_set_schedule", "iga_ensemble_set_window_schedule",
             "iga_ensemble_set_assembly_rows", "iga_ensemble_autotune", "iga_step_forced",
-            "iga_plan_quadrature_points", "iga_plan_set_column_schedule", "iga_last_error")
+            "iga_plan_quadrature_points", "iga_plan_set_column_schedule",
+            "iga_plan_set_assembly_stacking", "iga_plan_assembly_stacking",
+            "iga_ensemble_set_assembly_stacking", "iga_last_error")
 
 _COEFF_NAMES = ("c_adv", "c_diff", "c_react", "c_nld", "c_ign", "t_ig", "fuel_thr", "t_act",
                 "c_forcing", "c_rad", "fuel_rate")
@@ -108,10 +110,14 @@ def lib() -> ctypes.CDLL:
         L.iga_step_forced.argtypes = [vp, vp, vp, vp, vp, vp]
         L.iga_plan_set_column_schedule.argtypes = [vp, i32]
         L.iga_plan_quadrature_points.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_double)]
+        L.iga_plan_set_assembly_stacking.argtypes = [vp, i32]
+        L.iga_plan_assembly_stacking.argtypes = [vp]
+        L.iga_plan_assembly_stacking.restype = i32
+        L.iga_ensemble_set_assembly_stacking.argtypes = [vp, i32]
         L.iga_last_error.argtypes = []
         L.iga_last_error.restype = ctypes.c_char_p
         for name in EXPORTED[1:-1]:
-            if name != "iga_plan_assembly_rows":
+            if name not in ("iga_plan_assembly_rows", "iga_plan_assembly_stacking"):
                 getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -287,6 +293,14 @@ class Plan:
     def set_assembly_rows(self, rows):
         _check(lib().iga_plan_set_assembly_rows(self._h, int(rows)), "iga_plan_set_assembly_rows")
 
+    @property
+    def assembly_stacked(self) -> bool:
+        return bool(lib().iga_plan_assembly_stacking(self._h))
+
+    def set_assembly_stacking(self, stacked):
+        _check(lib().iga_plan_set_assembly_stacking(self._h, int(stacked)),
+               "iga_plan_set_assembly_stacking")
+
     def set_window_schedule(self, dir, lines, rows_per_lane=0):
         _check(lib().iga_plan_set_window_schedule(self._h, int(dir), int(lines), int(rows_per_lane)),
                "iga_plan_set_window_schedule")
@@ -380,6 +394,10 @@ class Ensemble:
     def set_assembly_rows(self, rows):
         _check(lib().iga_ensemble_set_assembly_rows(self._h, int(rows)),
                "iga_ensemble_set_assembly_rows")
+
+    def set_assembly_stacking(self, stacked):
+        _check(lib().iga_ensemble_set_assembly_stacking(self._h, int(stacked)),
+               "iga_ensemble_set_assembly_stacking")
 
     def autotune(self, Ts, Fs, reps=10, stream=None):
         _check(lib().iga_ensemble_autotune(self._h, self._fields(Ts, "T"), self._fields(Fs, "fuel"),

@@ -126,6 +126,41 @@ def test_members_match_own_plans_and_oracle(p, precision):
     ens.close()
 
 
+@pytest.mark.parametrize("p", [2, 3])
+@pytest.mark.parametrize("stacked", [True, False])
+def test_members_at_smallest_tile_height(p, stacked):
+    """The batched assembly with four-tile workgroups at tile height p + 1
+    (the most shared halos when stacked): members against their own plans and
+    the oracle."""
+    scs = members(p)
+    ens = iga.Ensemble.from_scenarios(scs, precision="fp64")
+    ens.set_assembly_rows(p + 1)
+    ens.set_assembly_stacking(stacked)
+    Ts, Fs = fields(ens, scs)
+    plans = []
+    for sc in scs:
+        pl = iga.Plan.from_scenario(sc)
+        pl.factor()
+        pl.set_schedule(0, 4, 0)
+        pl.set_schedule(1, 2, 0)
+        pl.set_assembly_rows(p + 1)
+        pl.set_assembly_stacking(stacked)
+        plans.append(pl)
+    Tp, Fp = fields(ens, scs)
+    prev = [(host(T), host(F)) for T, F in zip(Ts, Fs)]
+    ens.step(Ts, Fs)
+    for m, pl in enumerate(plans):
+        pl.step(Tp[m], Fp[m])
+        T, F = host(Ts[m]), host(Fs[m])
+        assert rel(T, host(Tp[m])) < 1e-13 and rel(F, host(Fp[m])) < 1e-13, m
+        check_vs_oracle(scs[m], T, F, prev[m][0], prev[m][1], "fp64")
+        pl.close()
+    with pytest.raises(iga.IgaError) as e:
+        ens.set_assembly_rows(p)
+    assert e.value.status == iga.EINVAL
+    ens.close()
+
+
 def test_run_graph_equals_eager_steps():
     scs = members(2)
     ens = iga.Ensemble.from_scenarios(scs, precision="fp32")

@@ -241,6 +241,67 @@ def test_assemble_fp64(nx, ny, p, scheme):
         assert rel(host(rf), RFref) < TOL64
 
 
+def tile_meshes(p, r):
+    """Element rows around the assembly's group boundaries for tile height r
+    (a group covers 4r - p dof rows, nel + p dof rows in all): exactly one
+    group, one and two rows past it, a one-row tile in the second wavefront
+    of the next group, the smallest mesh, and a ragged one."""
+    g = 4 * r - p
+    small = 2 * p + 1   # the smallest mesh a plan accepts
+    return sorted({n for n in (g - p, g - p + 1, g - p + 2, g + r - 2 * p + 1, small, 97) if n >= small})
+
+
+@pytest.mark.parametrize("p", [1, 2, 3])
+@pytest.mark.parametrize("rows", [0, 5, 7, 13, 64])
+@pytest.mark.parametrize("stacked", [True, False])
+def test_assemble_every_tile_height(p, rows, stacked):
+    """Four-tile workgroups, with halos shared in LDS (stacked) or evaluated
+    per tile: the FP64 assembly (both substeps, with fuel, hot enough to
+    ignite) against the oracle, and one FP32 step, for tile heights from
+    p + 1 (rows = 0 here) up, on meshes that end at and just past group
+    boundaries."""
+    r = rows or p + 1
+    for nx in tile_meshes(p, r):
+        print(f"tile height {r} p{p} stacked {stacked} nel_x {nx}", flush=True)
+        sc = inputs.small_case(500 + nx, nx, 70, p, "strang")
+        pl, od = plan_and_oracle(sc)
+        pl.set_assembly_rows(r)
+        pl.set_assembly_stacking(stacked)
+        assert pl.assembly_rows == r and pl.assembly_stacked == stacked
+        T = sc.T0 + np.random.default_rng(nx).uniform(0, 600, sc.T0.shape)
+        for substep in substeps("strang"):
+            Rref, RFref = oracle.assemble(od, substep, T, sc.fuel0, with_fuel=True)
+            t, f = dev(T), dev(sc.fuel0)
+            rr, rf = torch.zeros_like(t), torch.zeros_like(t)
+            pl.assemble_rhs(substep, t, f, rr, rf)
+            assert rel(host(rr), Rref) < TOL64, (nx, substep)
+            assert rel(host(rf), RFref) < TOL64, (nx, substep)
+        pl.close()
+        pl, od = plan_and_oracle(sc, "fp32")
+        pl.set_assembly_rows(r)
+        pl.set_assembly_stacking(stacked)
+        T32, F32 = sc.T0.astype(np.float32), sc.fuel0.astype(np.float32)
+        t, f = dev(T32, True), dev(F32, True)
+        To, Fo = oracle.step(od, T32.astype(np.float64), F32.astype(np.float64))
+        pl.step(t, f)
+        assert rel(host(t), To) < TOL32 and rel(host(f), Fo) < TOL32, nx
+        pl.close()
+
+
+def test_assembly_schedule_argument_errors():
+    for p in (1, 2, 3):
+        sc = inputs.small_case(9, 20, 20, p, "pr")
+        pl = iga.Plan.from_scenario(sc)
+        with pytest.raises(iga.IgaError) as e:
+            pl.set_assembly_rows(p)
+        assert e.value.status == iga.EINVAL
+        pl.set_assembly_rows(p + 1)
+        with pytest.raises(iga.IgaError) as e:
+            pl.set_assembly_stacking(2)
+        assert e.value.status == iga.EINVAL
+        pl.close()
+
+
 @pytest.mark.parametrize("nx,ny,p,scheme", CASES)
 def test_steps_fp64(nx, ny, p, scheme):
     print(f"steps fp64 {nx}x{ny} p{p} {scheme}", flush=True)
