@@ -257,11 +257,12 @@ iga_status iga_plan_set_assembly_stacking(iga_plan *plan, int32_t stacked);
 int32_t iga_plan_assembly_stacking(const iga_plan *plan);
 
 /* Autotuner: times, with HIP events on `stream`, the assembly of the first
- * substep for several element-row tiles and the line solves of each direction
- * for every windowed and exact schedule that fits, on the plan's scratch
- * buffers (T and fuel are only read), and keeps the fastest of each (column
- * waves included for the x-lines of FP32 plans).  Synchronises `stream`; must
- * follow iga_factor_1d.  reps >= 1 launches per candidate. */
+ * substep for every tile height (stacked and unstacked) and the line solves
+ * of each direction for every windowed and exact schedule that fits, on the
+ * plan's scratch buffers (T and fuel are only read), and keeps the fastest
+ * of each (column waves included for the x-lines of FP32 plans).
+ * Synchronises `stream`; must follow iga_factor_1d.  reps >= 1 launches per
+ * candidate. */
 iga_status iga_autotune(iga_plan *plan, const void *T, const void *fuel, int32_t reps,
                         void *stream);
 
@@ -322,9 +323,12 @@ iga_status iga_ensemble_set_assembly_rows(iga_ensemble *ens, int32_t rows);
 /* As iga_plan_set_assembly_stacking, on every member. */
 iga_status iga_ensemble_set_assembly_stacking(iga_ensemble *ens, int32_t stacked);
 
-/* Autotuner of the batched launches: element-row tiles of the assembly, and
- * (lines, waves per line) per direction, timed with HIP events on `stream` on
- * the members' scratch buffers (the fields are only read).  Synchronises. */
+/* Autotuner of the batched launches: tile height and stacking of the
+ * assembly, and the line-solve schedule of each direction (windowed rows per
+ * lane or exact waves per line, lines per workgroup) timed on both of the
+ * step's launches of that direction with the step's own jobs; all timed with
+ * HIP events on `stream` on the members' scratch buffers (the fields are
+ * only read).  Synchronises. */
 iga_status iga_ensemble_autotune(iga_ensemble *ens, void *const *T, void *const *fuel, int32_t reps,
                                  void *stream);
 

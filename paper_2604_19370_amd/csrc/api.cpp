@@ -465,7 +465,7 @@ iga_status iga_autotune(iga_plan *plan, const void *T, const void *fuel, int32_t
     DevBuf out;   // two output fields, so the two jobs of a launch never share one
     IGA_HIP(out.alloc(2 * plan->ndof * plan->wsize));
     void *out2 = out.as<char>() + plan->ndof * plan->wsize;
-    // assembly: element rows marched per wavefront
+    // assembly: dof rows per wavefront tile, stacked or not
     {
         int best = plan->asm_rows, best_stack = plan->asm_stack;
         float best_ms = 1e30f;
