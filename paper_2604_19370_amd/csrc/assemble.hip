@@ -27,12 +27,13 @@
 // registers, evaluates the pointwise terms at the (p+1)^2 points and
 // accumulates the x half of the test-function contraction into per-row
 // accumulators.  When a dof row is complete its y contraction is gathered from
-// the p neighbouring lanes and stored.  A workgroup's four wavefronts take
-// four consecutive tiles of one strip; the p dof rows where two of its tiles
-// meet are summed in two parts (the upper tile's elements, then the lower
-// one's) that meet in LDS, so only the first tile re-evaluates the p elements
-// above it.  Every dof is summed by one lane, or two parts by two fixed
-// lanes, in a fixed order: no atomics, deterministic.
+// the p neighbouring lanes and stored.  In the stacked variant a workgroup's
+// four wavefronts take four consecutive tiles of one strip; the p dof rows
+// where two of its tiles meet are summed in two parts (the upper tile's
+// elements, then the lower one's) that meet in LDS, so only the first tile
+// re-evaluates the p elements above it (in the unstacked variant every tile
+// does).  Every dof is summed by one lane, or two parts by two fixed lanes,
+// in a fixed order: no atomics, deterministic.
 //
 // The marching loop is unrolled by p+1, so the rolling windows (coefficient
 // rows, accumulators, pending loads) are renamed, not copied.  The x
