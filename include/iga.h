@@ -315,8 +315,13 @@ iga_status iga_ensemble_run(iga_ensemble *ens, void *const *T, void *const *fuel
 iga_status iga_ensemble_set_schedule(iga_ensemble *ens, int32_t dir, int32_t lines,
                                      int32_t waves_per_line);
 /* Windowed line solves (as iga_plan_set_window_schedule) on every member
- * that allows them, the exact schedule with the same lines elsewhere.  The
- * default after iga_ensemble_create is (4, 17) along x and (2, 17) along y. */
+ * that allows them, the exact schedule with the same lines elsewhere.
+ * `lines` applies to the members whose lines need the most wavefronts; a
+ * member needing 1/f of them takes f times the lines per workgroup where
+ * that fits, so that its workgroups have the same size and it shares their
+ * launch (members of one launch share rows per lane and workgroup size).
+ * The default after iga_ensemble_create is (4, 17) along x and (2, 17) along
+ * y. */
 iga_status iga_ensemble_set_window_schedule(iga_ensemble *ens, int32_t dir, int32_t lines,
                                             int32_t rows_per_lane);
 iga_status iga_ensemble_set_assembly_rows(iga_ensemble *ens, int32_t rows);

@@ -126,15 +126,29 @@ iga_status set_schedule_all(iga_ensemble *e, int dir, int lines, int wpl)
 }
 
 // windowed schedule of one direction on every member (`lines` lines per
-// workgroup, mm rows per lane); members whose operators do not allow it get
-// the exact schedule with the same lines and the fewest waves per line
+// workgroup for the members with the longest lines, mm rows per lane);
+// members whose operators do not allow it get the exact schedule with the
+// same lines and the fewest waves per line.  A member whose lines need 1/f of
+// the wavefronts takes f times the lines per workgroup where that fits, so
+// that its workgroups have the same shape and it shares their launch.
 iga_status set_window_all(iga_ensemble *e, int dir, int lines, int mm)
 {
+    auto waves = [&](const iga_plan *pl) {
+        const int N = dir ? pl->Ny : pl->Nx;
+        return (N + 64 * mm - 1) / (64 * mm);
+    };
+    int wmax = 1;
+    for (const iga_plan *pl : e->plans) wmax = std::max(wmax, waves(pl));
     for (iga_plan *pl : e->plans) {
+        const int w = waves(pl), f = wmax / w;
+        if (wmax % w == 0 && f > 1 && (f & (f - 1)) == 0 && lines * f <= 16 &&
+            choose_window_schedule(pl, dir, lines * f, mm) == IGA_OK)
+            continue;
+        (void)hipGetLastError();
         if (choose_window_schedule(pl, dir, lines, mm) == IGA_OK) continue;
         (void)hipGetLastError();   // the fallback below is deliberate
         iga_status st = IGA_EUNSUPPORTED;
-        for (int w = 1; w <= 8 && st; w *= 2) st = choose_schedule(pl, dir, lines, w);
+        for (int ww = 1; ww <= 8 && st; ww *= 2) st = choose_schedule(pl, dir, lines, ww);
         if (st) return st;
     }
     set_error("");
@@ -152,7 +166,7 @@ int groups(const iga_ensemble *e, int dir, bool second = false)
         const Schedule &s = pl->sched[dir];
         bool found = false;
         for (const Schedule &t : seen)
-            found = found || (t.mm == s.mm && t.lines == s.lines && t.wpl == s.wpl && t.win == s.win);
+            found = found || (t.mm == s.mm && t.lines * t.wpl == s.lines * s.wpl && t.win == s.win);
         if (!found) seen.push_back(s);
     }
     return (int)seen.size();

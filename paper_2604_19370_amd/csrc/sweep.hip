@@ -271,7 +271,9 @@ iga_status build_sweep_batch(const std::vector<iga_plan *> &pls, int dir,
         size_t lds = 0;
         for (size_t m = m0; m < pls.size(); ++m) {
             const Schedule &sc = pls[m]->sched[dir];
-            if (done[m] || sc.mm != key.mm || sc.lines != key.lines || sc.wpl != key.wpl ||
+            // one launch per workgroup shape: members whose lines need fewer
+            // wavefronts join with proportionally more lines per workgroup
+            if (done[m] || sc.mm != key.mm || sc.lines * sc.wpl != key.lines * key.wpl ||
                 sc.win != key.win)
                 continue;
             done[m] = 1;
