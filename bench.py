@@ -322,8 +322,8 @@ def cpu_baseline(sc, budget_s):
 def main():
     args = parse()
     if args.gpus != 1:
-        print("bench.py: this stepper runs on one GPU; multi-GPU runs are not part of this "
-              "build (ensemble members would shard across GPUs with no exchange)", file=sys.stderr)
+        print("bench.py: this stepper runs on one GPU only; use --gpus 1 (ensemble members "
+              "would shard across GPUs with no exchange, one process per GPU)", file=sys.stderr)
         sys.exit(2)
     import torch
 

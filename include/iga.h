@@ -50,7 +50,7 @@ typedef enum {
     IGA_ENOMEM = 2,       /* device or host allocation failed               */
     IGA_EDEVICE = 3,      /* a HIP runtime call or kernel launch failed     */
     IGA_ENONFINITE = 4,   /* iga_run found a NaN/Inf in the state            */
-    IGA_EUNSUPPORTED = 5, /* valid request this build does not implement    */
+    IGA_EUNSUPPORTED = 5, /* valid request the library does not implement    */
     IGA_ESTATE = 6        /* call out of order (e.g. step before factor)    */
 } iga_status;
 
