@@ -358,6 +358,32 @@ __device__ __forceinline__ void stage_table(U *dst, const void *src, int n)
     }
 }
 
+// copy `nwords` 32-bit words from global `g` straight into LDS `lds` with the
+// whole workgroup (global_load_lds: no registers, every load in flight at
+// once).  Instruction k of the copy moves words [64k, 64k + 64); lane i
+// writes LDS word 64k + i.  The data are visible to the workgroup after the
+// next barrier (the compiler waits for the transfers there).
+__device__ __forceinline__ void lds_dma_words(void *lds, const void *g, int nwords)
+{
+    typedef __attribute__((address_space(1))) const void gvoid;
+    typedef __attribute__((address_space(3))) void lvoid;
+    const int lane = threadIdx.x & 63;
+    const int nw = blockDim.x >> 6;
+    const unsigned *src = static_cast<const unsigned *>(g);
+    unsigned *dst = static_cast<unsigned *>(lds);
+    for (int k = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6); k * 64 < nwords; k += nw) {
+        const int i = k * 64 + lane;
+        if (i < nwords) __builtin_amdgcn_global_load_lds((gvoid *)(src + i), (lvoid *)(dst + k * 64), 4, 0, 0);
+    }
+}
+
+// a table of n elements of type U, staged by DMA (sizes are whole words)
+template <typename U> __device__ __forceinline__ void stage_table_dma(U *dst, const void *src, int n)
+{
+    static_assert(sizeof(U) % 4 == 0, "tables hold 32- or 64-bit elements");
+    lds_dma_words(dst, src, (int)(n * sizeof(U) / 4));
+}
+
 // workgroup size bound: 16 wavefronts, or 8 where cubic double chunks of 12+
 // rows need more than 128 registers
 template <typename T, int P, int MM> constexpr int sweep_max_threads()
@@ -397,18 +423,18 @@ __device__ __forceinline__ void sweep_body(const SweepParams &prm, const int blk
     };
     auto stage_op = [&](const OpTab &t, OpView<T> &v) {
         T *rows = reinterpret_cast<T *>(take((size_t)t.nrows * RS * sizeof(T)));
-        stage_table<T>(rows, t.rows, t.nrows * RS);
+        stage_table_dma<T>(rows, t.rows, t.nrows * RS);
         v.rows = rows;
         v.a64 = nullptr;
         if (F32) {
             double *a = reinterpret_cast<double *>(take((size_t)t.nrows * RS * sizeof(double)));
-            stage_table<double>(a, t.a64, t.nrows * RS);
+            stage_table_dma<double>(a, t.a64, t.nrows * RS);
             v.a64 = a;
         }
         T *tf = reinterpret_cast<T *>(take((size_t)C * PP * sizeof(T)));
         T *tb = reinterpret_cast<T *>(take((size_t)C * PP * sizeof(T)));
-        stage_table<T>(tf, t.tf, C * PP);
-        stage_table<T>(tb, t.tb, C * PP);
+        stage_table_dma<T>(tf, t.tf, C * PP);
+        stage_table_dma<T>(tb, t.tb, C * PP);
         v.tf = tf;
         v.tb = tb;
         v.rm = RowMap{t.K0, t.NK - 1, t.nrows - 1};
@@ -422,7 +448,7 @@ __device__ __forceinline__ void sweep_body(const SweepParams &prm, const int blk
     if (hasb) {
         const BandTab &t = prm.bands[job.band];
         T *rows = reinterpret_cast<T *>(take((size_t)t.nrows * RS * sizeof(T)));
-        stage_table<T>(rows, t.rows, t.nrows * RS);
+        stage_table_dma<T>(rows, t.rows, t.nrows * RS);
         brow = rows;
         brm = RowMap{t.K0, t.NK - 1, t.nrows - 1};
     }

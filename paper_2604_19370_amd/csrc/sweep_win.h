@@ -337,11 +337,11 @@ __device__ __forceinline__ void wsweep_body(const WSweepParams &prm, const int b
     const double *a640 = nullptr, *a641 = nullptr;
     auto stage_op = [&](const WinOpTab &t, const T *&rows, const double *&a) {
         T *r = reinterpret_cast<T *>(take((size_t)g.nrows * RS * sizeof(T)));
-        stage_table<T>(r, t.rows, g.nrows * RS);
+        stage_table_dma<T>(r, t.rows, g.nrows * RS);
         rows = r;
         if (F32) {
             double *d = reinterpret_cast<double *>(take((size_t)g.anrows * RS * sizeof(double)));
-            stage_table<double>(d, t.a64, g.anrows * RS);
+            stage_table_dma<double>(d, t.a64, g.anrows * RS);
             a = d;
         }
     };
@@ -352,7 +352,7 @@ __device__ __forceinline__ void wsweep_body(const WSweepParams &prm, const int b
     if (has1) stage_op(prm.ops[job.op1], tab1, a641);
     if (hasb) {
         T *r = reinterpret_cast<T *>(take((size_t)g.anrows * RS * sizeof(T)));
-        stage_table<T>(r, prm.bands[job.band].rows, g.anrows * RS);
+        stage_table_dma<T>(r, prm.bands[job.band].rows, g.anrows * RS);
         btab = r;
     }
     // zero the pads of every line buffer: [0, H) and [H + N, Lb)
