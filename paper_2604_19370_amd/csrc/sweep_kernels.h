@@ -415,6 +415,9 @@ __device__ __forceinline__ void sweep_body(const SweepParams &prm, const int blk
 
     // LDS: staged lines, then the tables of this job and the line exchange slots
     T *st = reinterpret_cast<T *>(smem);
+    // y-lines: the input block is copied by DMA while the tables are staged
+    if constexpr (DIRY)
+        lds_dma_words(st, static_cast<const T *>(job.src) + (size_t)line0 * ld, (int)(nl * N * sizeof(T) / 4));
     size_t off = ((size_t)W * Ns * sizeof(T) + 15) & ~(size_t)15;
     auto take = [&](size_t bytes) {
         unsigned char *p = smem + off;
@@ -463,28 +466,16 @@ __device__ __forceinline__ void sweep_body(const SweepParams &prm, const int blk
     ctx.xnb = reinterpret_cast<T *>(take((size_t)W * 2 * WPL * 2 * P * sizeof(T))) +
               (size_t)lw * 2 * WPL * 2 * P;
 
-    // Stage W lines of a field (src layout) into st, and back.  Loads are
-    // issued in batches of UNR per thread before their LDS stores so that
-    // their latencies overlap.  y-lines: the W rows are one contiguous block,
-    // copied flat (Ns == N).  x-lines: rows of W consecutive columns.
+    // Stage W lines of a field (src layout) into st, and back.  y-lines: the
+    // W rows are one contiguous block (Ns == N), copied straight into LDS by
+    // DMA, every load in flight at once.  x-lines: rows of W consecutive
+    // columns; loads are issued in batches of UNR per thread before their LDS
+    // stores so that their latencies overlap.
     constexpr int UNR = 8;
     auto load_lines = [&](const T *src) {
         if constexpr (DIRY) {
-            const T *s = src + (size_t)line0 * ld;
-            const int tot = nl * N;
-            for (int b0 = 0; b0 < tot; b0 += UNR * blockDim.x) {
-                T v[UNR];
-#pragma unroll
-                for (int u = 0; u < UNR; ++u) {
-                    const int e = b0 + u * blockDim.x + tid;
-                    v[u] = e < tot ? s[e] : T(0);
-                }
-#pragma unroll
-                for (int u = 0; u < UNR; ++u) {
-                    const int e = b0 + u * blockDim.x + tid;
-                    if (e < tot) st[e] = v[u];
-                }
-            }
+            // one contiguous run in HBM and in LDS: copied by DMA
+            lds_dma_words(st, src + (size_t)line0 * ld, (int)(nl * N * sizeof(T) / 4));
         } else {
             const int j = tid & (W - 1);
             const bool jok = j < nl;
@@ -517,7 +508,7 @@ __device__ __forceinline__ void sweep_body(const SweepParams &prm, const int blk
         }
     };
 
-    load_lines(static_cast<const T *>(job.src));
+    if constexpr (!DIRY) load_lines(static_cast<const T *>(job.src));
     __syncthreads();
 
     // this lane's chunk: rows [r0, r0 + MM) of line lw; rows >= N are padding
