@@ -114,9 +114,11 @@ __device__ __forceinline__ void assemble_body(const AsmParams<T> &a, const int s
     }
 
     // raw coefficients of row `row` for columns colA (and colB for the halo)
+    // (rows past the tile's last element are never used: not loaded)
+    const int rlim = min(X1, a.nel_x) + P;
     auto fetch = [&](int row, T &c0, T &c1, T &f0, T &f1) {
         c0 = c1 = f0 = f1 = T(0);
-        if (row >= 0 && row < a.Nx) {
+        if (row >= 0 && row < rlim) {
             const size_t base = (size_t)row * Ny;
             if (okA) {
                 c0 = a.S[base + colA];
