@@ -375,18 +375,33 @@ def test_plain_pr_64_twenty_steps_fp64():
         assert rel(host(f), F) < TOL64, k
 
 
-def test_run_graph_equals_eager_steps_bitwise():
+@pytest.mark.parametrize("precision,stacked", [("fp64", False), ("fp64", True),
+                                               ("fp32", False), ("fp32", True)])
+def test_run_graph_equals_eager_steps_bitwise(precision, stacked):
+    """Graph-replayed steps equal eager ones bit for bit (no atomics, fixed
+    summation order), replay after replay, for both assembly tilings."""
     sc = inputs.small_case(9, 90, 70, 2, "strang", dt=2e-3)
-    pl, _ = plan_and_oracle(sc)
-    t1, f1 = dev(sc.T0), dev(sc.fuel0)
-    t2, f2 = dev(sc.T0), dev(sc.fuel0)
+    fp32 = precision == "fp32"
+    pl, _ = plan_and_oracle(sc, precision)
+    pl.set_assembly_rows(5)
+    pl.set_assembly_stacking(stacked)
+    t1, f1 = dev(sc.T0, fp32), dev(sc.fuel0, fp32)
+    t2, f2 = dev(sc.T0, fp32), dev(sc.fuel0, fp32)
     for _ in range(37):
         pl.step(t1, f1)
     pl.run(t2, f2, 37)        # one captured graph of 37 steps
     assert torch.equal(t1, t2) and torch.equal(f1, f2)
-    t3, f3 = dev(sc.T0), dev(sc.fuel0)
-    pl.run(t3, f3, 37)
-    assert torch.equal(t3, t2) and torch.equal(f3, f2)
+    ref_t, ref_f = t2.clone(), f2.clone()
+    for _ in range(2):        # replays of the same graph (same buffers), eager work in between
+        t2.copy_(dev(sc.T0, fp32))
+        f2.copy_(dev(sc.fuel0, fp32))
+        torch.cuda.synchronize()
+        pl.run(t2, f2, 37)
+        assert torch.equal(t2, ref_t) and torch.equal(f2, ref_f)
+    t3, f3 = dev(sc.T0, fp32), dev(sc.fuel0, fp32)
+    pl.run(t3, f3, 37)        # new buffers: captured again
+    assert torch.equal(t3, ref_t) and torch.equal(f3, ref_f)
+    pl.close()
 
 
 def test_invalid_calls_on_device():
