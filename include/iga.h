@@ -324,6 +324,7 @@ iga_status iga_ensemble_set_schedule(iga_ensemble *ens, int32_t dir, int32_t lin
  * y. */
 iga_status iga_ensemble_set_window_schedule(iga_ensemble *ens, int32_t dir, int32_t lines,
                                             int32_t rows_per_lane);
+/* As iga_plan_set_assembly_rows, on every member (rows >= p + 1). */
 iga_status iga_ensemble_set_assembly_rows(iga_ensemble *ens, int32_t rows);
 /* As iga_plan_set_assembly_stacking, on every member. */
 iga_status iga_ensemble_set_assembly_stacking(iga_ensemble *ens, int32_t stacked);
