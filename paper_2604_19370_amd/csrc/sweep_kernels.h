@@ -336,28 +336,6 @@ __device__ __forceinline__ void solve_refined(T (&x)[MM], const OpView<T> &op, L
     }
 }
 
-// copy `n` elements of type U from global to LDS with the whole workgroup
-// (eight loads in flight per thread)
-template <typename U>
-__device__ __forceinline__ void stage_table(U *dst, const void *src, int n)
-{
-    constexpr int UNR = 8;
-    const U *s = static_cast<const U *>(src);
-    for (int b0 = 0; b0 < n; b0 += UNR * blockDim.x) {
-        U v[UNR];
-#pragma unroll
-        for (int u = 0; u < UNR; ++u) {
-            const int i = b0 + u * blockDim.x + threadIdx.x;
-            v[u] = i < n ? s[i] : U(0);
-        }
-#pragma unroll
-        for (int u = 0; u < UNR; ++u) {
-            const int i = b0 + u * blockDim.x + threadIdx.x;
-            if (i < n) dst[i] = v[u];
-        }
-    }
-}
-
 // copy `nwords` 32-bit words from global `g` straight into LDS `lds` with the
 // whole workgroup (global_load_lds: no registers, every load in flight at
 // once).  Instruction k of the copy moves words [64k, 64k + 64); lane i
