@@ -47,6 +47,8 @@ def parse():
     ap.add_argument("--window-schedule", type=str, default=None,
                     help="fixed windowed line-solve schedule 'xlines,xrows,ylines,yrows,asmrows' "
                          "(rows per lane) instead of autotuning")
+    ap.add_argument("--no-other-schemes", action="store_true",
+                    help="skip the PR and explicit-scheme lines at the same size")
     ap.add_argument("--no-ensembles", action="store_true",
                     help="skip the ensemble workloads (64 uneven members; 16 cubic 2048^2 members)")
     ap.add_argument("--no-paper-meshes", action="store_true",
@@ -261,6 +263,29 @@ def ensembles(torch, iga, inputs):
     return res
 
 
+def other_schemes(nel, steps, torch, iga, inputs):
+    """The other two schemes on the same regional inputs: Peaceman-Rachford
+    (6 launches per step) and the explicit L2 projection of Section 6.1 (3
+    launches per step), FP32+refine and FP64, autotuned, graph-replayed."""
+    out = {}
+    for scheme in ("pr", "explicit"):
+        sc = inputs.regional_strang(seed=1, nel=nel, steps=steps)
+        sc.scheme = scheme
+        for prec in ("fp32", "fp64"):
+            pl = iga.Plan.from_scenario(sc, precision=prec)
+            pl.factor()
+            Tt = torch.tensor(sc.T0, dtype=pl.dtype, device="cuda")
+            Ft = torch.tensor(sc.fuel0, dtype=pl.dtype, device="cuda")
+            pl.autotune(Tt, Ft, reps=5)
+            del Tt, Ft
+            wall, ev, T, F = time_steps(pl, sc, steps, 5, torch)
+            out[f"{scheme}_{prec}"] = {"value": round(sc.ndof * steps / wall, 1),
+                                       "unit": "DOF-steps/s",
+                                       "ms_per_step": round(wall / steps * 1e3, 5)}
+            pl.close()
+    return out
+
+
 # The meshes and step counts of the paper's CPU scalability study (Section 7):
 # 100^2 / 600^2 / 1500^2 elements, 120 / 720 / 1080 steps, p = 1, 2, 3.  The
 # paper does not state the scheme or the inputs of those runs; here they are
@@ -398,6 +423,8 @@ def main():
         "roofline": roof,
         "schedules": res["fp32"]["sched"],
     }
+    if not args.no_other_schemes:
+        line["other_schemes"] = other_schemes(args.nel, args.steps, torch, iga, inputs)
     if not args.no_ensembles:
         line["ensembles"] = ensembles(torch, iga, inputs)
     if not args.no_paper_meshes:
