@@ -33,7 +33,9 @@
 // elements, then the lower one's) that meet in LDS, so only the first tile
 // re-evaluates the p elements above it (in the unstacked variant every tile
 // does).  Every dof is summed by one lane, or two parts by two fixed lanes,
-// in a fixed order: no atomics, deterministic.
+// in a fixed order: no atomics, deterministic.  The right-hand sides are
+// stored non-temporally (streamed out of L2): the sweep that reads them next
+// runs on every XCD.
 //
 // The marching loop is unrolled by p+1, so the rolling windows (coefficient
 // rows, accumulators, pending loads) are renamed, not copied.  The x
@@ -321,8 +323,8 @@ __device__ __forceinline__ void assemble_body(const AsmParams<T> &a, const int s
                 tl[ti * 64 + lane] = r;
                 if (FUEL) tl[(P + ti) * 64 + lane] = rf;
             } else if (lane >= P && colA < Ny) {
-                a.R[(size_t)ex * Ny + colA] = r;
-                if (FUEL) a.RF[(size_t)ex * Ny + colA] = rf;
+                __builtin_nontemporal_store(r, &a.R[(size_t)ex * Ny + colA]);
+                if (FUEL) __builtin_nontemporal_store(rf, &a.RF[(size_t)ex * Ny + colA]);
             }
         }
         if (FUEL) {
@@ -394,9 +396,9 @@ __device__ __forceinline__ void assemble_group(const AsmParams<T> &a, const int 
 #pragma unroll
                 for (int i = 0; i < P; ++i) {
                     const size_t o = (size_t)(X0 + i) * a.Ny + colA;
-                    a.R[o] = part[1][w - 1][i * 64 + lane] + part[0][w][i * 64 + lane];
+                    __builtin_nontemporal_store(part[1][w - 1][i * 64 + lane] + part[0][w][i * 64 + lane], &a.R[o]);
                     if (FUEL)
-                        a.RF[o] = part[1][w - 1][(P + i) * 64 + lane] + part[0][w][(P + i) * 64 + lane];
+                        __builtin_nontemporal_store(part[1][w - 1][(P + i) * 64 + lane] + part[0][w][(P + i) * 64 + lane], &a.RF[o]);
                 }
             }
         }
