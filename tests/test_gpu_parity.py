@@ -404,6 +404,27 @@ def test_run_graph_equals_eager_steps_bitwise(precision, stacked):
     pl.close()
 
 
+@pytest.mark.parametrize("precision,scheme", [("fp64", "pr"), ("fp64", "strang"),
+                                              ("fp32", "strang"), ("fp32", "explicit")])
+def test_restart_from_host_checkpoint_is_bitwise(precision, scheme):
+    """The state of a run is (T, fuel): a run stopped after 13 steps, copied to
+    host memory and resumed from fresh device buffers for 17 more ends bit for
+    bit where an unsplit 30-step run ends."""
+    sc = inputs.small_case(11, 70, 90, 2, scheme, dt=2e-3)
+    fp32 = precision == "fp32"
+    pl, _ = plan_and_oracle(sc, precision)
+    t1, f1 = dev(sc.T0, fp32), dev(sc.fuel0, fp32)
+    pl.run(t1, f1, 30)
+    t2, f2 = dev(sc.T0, fp32), dev(sc.fuel0, fp32)
+    pl.run(t2, f2, 13)
+    ck_t, ck_f = host(t2), host(f2)     # exact for both precisions
+    del t2, f2
+    t3, f3 = dev(ck_t, fp32), dev(ck_f, fp32)
+    pl.run(t3, f3, 17)
+    assert torch.equal(t3, t1) and torch.equal(f3, f1)
+    pl.close()
+
+
 def test_invalid_calls_on_device():
     sc = inputs.small_case(1, 20, 20, 2, "strang")
     pl = iga.Plan.from_scenario(sc)
