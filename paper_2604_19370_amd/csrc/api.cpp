@@ -1,8 +1,11 @@
 // api.cpp -- the C ABI (include/iga.h): argument checking, the step
 // sequences of the schemes, and the graph-replayed run loop.
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <new>
+#include <utility>
+#include <vector>
 
 #include "iga_internal.h"
 
@@ -466,6 +469,7 @@ iga_status iga_autotune(iga_plan *plan, const void *T, const void *fuel, int32_t
     IGA_HIP(out.alloc(2 * plan->ndof * plan->wsize));
     void *out2 = out.as<char>() + plan->ndof * plan->wsize;
     // assembly: dof rows per wavefront tile, stacked or not
+    std::vector<std::pair<float, std::pair<int, int>>> asm_timed;   // (ms, (rows, stacked))
     {
         int best = plan->asm_rows, best_stack = plan->asm_stack;
         float best_ms = 1e30f;
@@ -476,6 +480,7 @@ iga_status iga_autotune(iga_plan *plan, const void *T, const void *fuel, int32_t
                 plan->asm_stack = stack;
                 float ms =
                     time_launches(s, reps, [&] { return launch_assemble(plan, 0, T, fuel, R, RF, s); });
+                if (ms >= 0) asm_timed.emplace_back(ms, std::make_pair(rows, stack));
                 if (ms >= 0 && ms < best_ms) {
                     best_ms = ms;
                     best = rows;
@@ -489,6 +494,12 @@ iga_status iga_autotune(iga_plan *plan, const void *T, const void *fuel, int32_t
     // line solves: lines per workgroup, timed on the step's own jobs
     const void *bT = plan->delta ? T : nullptr;
     const int add = plan->delta ? 1 : 0;
+    auto apply = [&](int dir, const Schedule &sc) {
+        if (sc.col) return choose_column_schedule(plan, sc.mm);
+        if (sc.win) return choose_window_schedule(plan, dir, sc.lines, sc.mm);
+        return choose_schedule(plan, dir, sc.lines, sc.wpl);
+    };
+    std::vector<std::pair<float, Schedule>> timed[2];   // every candidate, launched alone
     for (int dir = 0; dir < 2; ++dir) {
         SweepJob jobs[2];
         int nj;
@@ -508,6 +519,7 @@ iga_status iga_autotune(iga_plan *plan, const void *T, const void *fuel, int32_t
         float best_ms = 1e30f;
         auto consider = [&] {
             float ms = time_launches(s, reps, [&] { return launch_sweep(plan, dir, jobs, nj, s); });
+            if (ms >= 0) timed[dir].emplace_back(ms, plan->sched[dir]);
             if (ms >= 0 && ms < best_ms) {
                 best_ms = ms;
                 best = plan->sched[dir];
@@ -532,10 +544,70 @@ iga_status iga_autotune(iga_plan *plan, const void *T, const void *fuel, int32_t
                 consider();
             }
         }
-        if (best.col) st = choose_column_schedule(plan, best.mm);
-        else if (best.win) st = choose_window_schedule(plan, dir, best.lines, best.mm);
-        else st = choose_schedule(plan, dir, best.lines, best.wpl);
-        if (st) return st;
+        if ((st = apply(dir, best))) return st;
+    }
+    // Refinement: the fastest few assembly tilings, then the fastest few
+    // line-solve candidates of each direction, again, timed
+    // as graph-replayed steps (as iga_run executes them) on copies of T and
+    // fuel.  Inside a step a sweep reads what the kernel before it has just
+    // written from every XCD, which the launches above, repeated on the same
+    // input, do not show.
+    {
+        const size_t fb = plan->ndof * plan->wsize;
+        DevBuf state;
+        IGA_HIP(state.alloc(2 * fb));
+        void *sT = state.ptr, *sF = state.as<char>() + fb;
+        auto step_ms = [&]() -> float {
+            if (hipMemcpyAsync(sT, T, fb, hipMemcpyDeviceToDevice, s) != hipSuccess ||
+                hipMemcpyAsync(sF, fuel, fb, hipMemcpyDeviceToDevice, s) != hipSuccess)
+                return -1.f;
+            GraphEntry g;
+            float ms = -1.f;
+            if (capture(plan, g, sT, sF, reps) == IGA_OK)
+                ms = time_launches(s, 1, [&] {
+                    return hipGraphLaunch(g.exec, s) == hipSuccess ? IGA_OK : IGA_EDEVICE;
+                });
+            (void)hipStreamSynchronize(s);
+            g.reset();
+            return ms < 0 ? ms : ms / reps;
+        };
+        constexpr size_t NREFINE = 8;
+        std::stable_sort(asm_timed.begin(), asm_timed.end(),
+                         [](const auto &a, const auto &b) { return a.first < b.first; });
+        if (asm_timed.size() > 1) {
+            int best = plan->asm_rows, best_stack = plan->asm_stack;
+            float best_ms = 1e30f;
+            for (size_t i = 0; i < std::min(asm_timed.size(), NREFINE); ++i) {
+                plan->asm_rows = asm_timed[i].second.first;
+                plan->asm_stack = asm_timed[i].second.second;
+                const float ms = step_ms();
+                if (ms >= 0 && ms < best_ms) {
+                    best_ms = ms;
+                    best = plan->asm_rows;
+                    best_stack = plan->asm_stack;
+                }
+            }
+            plan->asm_rows = best;
+            plan->asm_stack = best_stack;
+        }
+        for (int dir = 0; dir < 2; ++dir) {
+            auto &c = timed[dir];
+            std::stable_sort(c.begin(), c.end(),
+                             [](const auto &a, const auto &b) { return a.first < b.first; });
+            if (c.size() < 2) continue;
+            Schedule best = plan->sched[dir];
+            float best_ms = 1e30f;
+            for (size_t i = 0; i < std::min(c.size(), NREFINE); ++i) {
+                if (apply(dir, c[i].second) != IGA_OK) continue;
+                const float ms = step_ms();
+                if (ms >= 0 && ms < best_ms) {
+                    best_ms = ms;
+                    best = c[i].second;
+                }
+            }
+            if ((st = apply(dir, best))) return st;
+        }
+        IGA_HIP(hipStreamSynchronize(s));
     }
     IGA_HIP(hipStreamSynchronize(s));
     plan->graph.reset();
