@@ -450,14 +450,74 @@ def test_explicit_and_implicit_wind_agree_to_second_order():
     assert 3.0 < diffs[0] / diffs[1] < 5.0
 
 
-def test_eval_grid_and_burned_fraction():
-    d = oracle.make_desc(8, 6, 2, 8.0, 6.0, 1e-3, "pr")
-    C = np.full((10, 8), 0.7)
-    v = oracle.eval_grid(d, C, np.linspace(0, 8, 5), np.linspace(0, 6, 4))
-    np.testing.assert_allclose(v, 0.7, atol=1e-14)
-    C[:5] = 0.0   # zero coefficients for x-functions 0..4 -> element columns 0..2 fully zero
-    bfrac = oracle.burned_fraction(d, C, 0.1)
-    assert 3 / 8 <= bfrac <= 5 / 8
+@pytest.mark.parametrize("p", [1, 2, 3])
+def test_eval_grid_matches_scipy_on_random_coefficients(p):
+    """The spline value sum_ij C_ij B_i(x) B_j(y) at arbitrary points, against
+    scipy's B-spline evaluation of the same coefficients (Bx C By^T), on a
+    grid with different element counts and lengths in x and y, so a swapped
+    index or length fails."""
+    nx, ny = 9, 6
+    Lx, Ly = 9 * 1.3, 6 * 0.7
+    d = oracle.make_desc(nx, ny, p, Lx, Ly, 1e-3, "pr")
+    rng = np.random.default_rng(10 + p)
+    C = rng.normal(size=(nx + p, ny + p))
+    xs = np.concatenate([rng.uniform(0, Lx, 23), [0.0, Lx, 2 * Lx / nx]])
+    ys = np.concatenate([rng.uniform(0, Ly, 17), [0.0, Ly, 3 * Ly / ny]])
+    got = oracle.eval_grid(d, C, xs, ys)
+    want = bf.basis(nx, p, Lx, xs) @ C @ bf.basis(ny, p, Ly, ys).T
+    assert got.shape == (xs.size, ys.size)
+    np.testing.assert_allclose(got, want, atol=1e-12 * np.abs(want).max())
+
+
+@pytest.mark.parametrize("p", [1, 2, 3])
+def test_eval_grid_reproduces_bilinear_fields_exactly(p):
+    """a + b x + c y + e x y lies in the spline space for p >= 1; its
+    coefficients are the same expression at the Greville abscissae
+    (Marsden's identity), so evaluation must return the polynomial."""
+    nx, ny = 11, 7
+    Lx, Ly = 11.0, 3.5
+    d = oracle.make_desc(nx, ny, p, Lx, Ly, 1e-3, "pr")
+    gx, gy = inputs.greville(nx, p) * Lx, inputs.greville(ny, p) * Ly
+    a, b, c, e = 300.0, 2.5, -7.0, 0.75
+    C = a + b * gx[:, None] + c * gy[None, :] + e * gx[:, None] * gy[None, :]
+    rng = np.random.default_rng(3)
+    xs, ys = rng.uniform(0, Lx, 31), rng.uniform(0, Ly, 13)
+    want = a + b * xs[:, None] + c * ys[None, :] + e * xs[:, None] * ys[None, :]
+    np.testing.assert_allclose(oracle.eval_grid(d, C, xs, ys), want, rtol=1e-13)
+
+
+def test_burned_fraction_exact_counts():
+    """Fuel linear in one coordinate (exact in the spline space): the
+    elements whose centre value is below the threshold can be counted by
+    hand.  x and y use different element counts, so a transposed sample
+    changes the count."""
+    nx, ny, p = 10, 40, 2
+    d = oracle.make_desc(nx, ny, p, 10.0, 20.0, 1e-3, "pr")
+    gx, gy = inputs.greville(nx, p), inputs.greville(ny, p)
+    # fuel = y / Ly: centres (e + 0.5) / 40 < 0.1 for e = 0..3 -> 4 of 40 rows
+    fy = np.broadcast_to(gy[None, :], (nx + p, ny + p)).copy()
+    assert oracle.burned_fraction(d, fy, 0.1) == 4 * nx / (nx * ny)
+    # fuel = 1 - x / Lx: centres 1 - (e + 0.5) / 10 < 0.1 for e = 9 only
+    fx = np.broadcast_to(1.0 - gx[:, None], (nx + p, ny + p)).copy()
+    assert oracle.burned_fraction(d, fx, 0.1) == ny / (nx * ny)
+    # threshold 0.5 on y / Ly: e + 0.5 < 20 for e = 0..19
+    assert oracle.burned_fraction(d, fy, 0.5) == 20 * nx / (nx * ny)
+    # fuel = x y / (Lx Ly) < 0.1: count centre pairs directly
+    fxy = gx[:, None] * gy[None, :]
+    cx, cy = (np.arange(nx) + 0.5) / nx, (np.arange(ny) + 0.5) / ny
+    want = int((cx[:, None] * cy[None, :] < 0.1).sum())
+    assert oracle.burned_fraction(d, fxy, 0.1) == want / (nx * ny)
+
+
+def test_burned_fraction_random_field_matches_scipy_count():
+    nx, ny, p = 13, 21, 3
+    d = oracle.make_desc(nx, ny, p, 13.0, 42.0, 1e-3, "pr")
+    C = np.random.default_rng(5).uniform(-0.2, 1.0, size=(nx + p, ny + p))
+    cx, cy = (np.arange(nx) + 0.5) * 13.0 / nx, (np.arange(ny) + 0.5) * 42.0 / ny
+    vals = bf.basis(nx, p, 13.0, cx) @ C @ bf.basis(ny, p, 42.0, cy).T
+    want = int((vals < 0.1).sum())
+    assert 0 < want < nx * ny
+    assert oracle.burned_fraction(d, C, 0.1) == want / (nx * ny)
 
 
 @pytest.mark.parametrize("scheme", ["pr", "strang", "explicit"])
