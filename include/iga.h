@@ -194,6 +194,23 @@ iga_status iga_plan_quadrature_points(const iga_plan *plan, int32_t dir, double 
  * IGA_ENONFINITE is returned at the first failure (state left as computed). */
 iga_status iga_run(iga_plan *plan, void *T, void *fuel, int64_t nsteps, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the step of
+ * iga_step, with the right-hand-side scratch taken from a fixed device array
+ * of IGA_NOALLOC_SCRATCH_BYTES that the library holds on each GPU it runs on
+ * until the process ends, instead of the plan's own buffers.  Calls no
+ * allocating routine.  The plan needs 2 fields (4 under column-wave x
+ * sweeps) of ndof * element size bytes, each rounded up to 256 bytes; a plan
+ * that needs more returns IGA_EINVAL (so at most about 8.3M dofs for FP32
+ * plans, 4.1M for FP64).  The first call on a device looks the array's
+ * address up once.  Every call on one GPU shares its array, which keeps the
+ * last call's contents (nothing in it has to start at zero): calls that
+ * overlap on one GPU -- two streams, or two host threads -- race, and the
+ * caller must serialise them.  Results equal iga_step's bit for bit.
+ * Requires iga_factor_1d; other errors as iga_step. */
+#define IGA_NOALLOC_SCRATCH_BYTES (64u << 20)
+iga_status iga_step_noalloc(iga_plan *plan, void *T, void *fuel, void *stream);
+
 /* Line-solve schedule of direction dir: lines per workgroup, wavefronts per
  * line, rows per lane (each line is split into 64 * waves_per_line chunks of
  * that many rows) and the largest compressed coefficient table (rows kept per

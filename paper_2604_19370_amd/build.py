@@ -26,7 +26,7 @@ FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
          "-Wall", "-Wno-unused-function", "-Wno-unused-variable",
          f"-I{os.path.join(ROOT, 'include')}"]
 
-SOURCES = ["plan.cpp", "api.cpp", "ensemble.cpp", "factor.hip", "assemble.hip", "sweep.hip",
+SOURCES = ["plan.cpp", "api.cpp", "noalloc.cpp", "ensemble.cpp", "factor.hip", "assemble.hip", "sweep.hip",
            "sweep_f1.hip", "sweep_f2.hip", "sweep_f3.hip", "sweep_d1.hip", "sweep_d2.hip",
            "sweep_d3.hip", "sweep_col.hip"]
 

@@ -77,11 +77,14 @@ iga_status check_field(const void *p, const char *name)
 // assembly, x sweep, y sweep, twice; an explicit step is the first three.
 // The x sweeps solve in place, or into second scratch fields under a
 // column-wave x schedule (whose waves read rows around their own chunk).
-void step_phases(const iga_plan *pl, void *T, void *fuel, StepPhases &sp)
+// work: NULL for the plan's scratch fields, else four fields (R, R_fuel and,
+// under column waves, their x-solved copies) that replace them.
+void step_phases(const iga_plan *pl, void *T, void *fuel, StepPhases &sp, void *const *work)
 {
-    void *R = pl->scratch_r.ptr, *RF = pl->scratch_rf.ptr;
+    void *R = work ? work[0] : pl->scratch_r.ptr, *RF = work ? work[1] : pl->scratch_rf.ptr;
     const bool col = pl->sched[0].col != 0;
-    void *XR = col ? pl->scratch_r2.ptr : R, *XRF = col ? pl->scratch_rf2.ptr : RF;
+    void *XR = col ? (work ? work[2] : pl->scratch_r2.ptr) : R;
+    void *XRF = col ? (work ? work[3] : pl->scratch_rf2.ptr) : RF;
     const void *bT = pl->delta ? T : nullptr, *bF = pl->delta ? fuel : nullptr;
     const int add = pl->delta ? 1 : 0;
     const bool pr = pl->d.scheme == IGA_PR;
@@ -116,12 +119,13 @@ void step_phases(const iga_plan *pl, void *T, void *fuel, StepPhases &sp)
     }
 }
 
-// src0 / src1: sources of the first / second quadrature substep (forced steps)
-static iga_status step_impl(iga_plan *pl, void *T, void *fuel, hipStream_t s,
-                            const void *src0 = nullptr, const void *src1 = nullptr)
+// src0 / src1: sources of the first / second quadrature substep (forced steps);
+// work: replacement scratch fields (see step_phases), or NULL
+iga_status step_impl(const iga_plan *pl, void *T, void *fuel, hipStream_t s, const void *src0,
+                     const void *src1, void *const *work)
 {
     StepPhases sp;
-    step_phases(pl, T, fuel, sp);
+    step_phases(pl, T, fuel, sp, work);
     iga_status st;
     auto sweep = [&](int dir, const std::vector<SweepJob> &j) {
         return launch_sweep(pl, dir, j.data(), (int)j.size(), s);

@@ -275,7 +275,12 @@ struct StepPhases {
     std::vector<SweepJob> x1, y1, x2, y2;
     bool two = true;   // false: the step is a1, x1, y1 only (explicit scheme)
 };
-void step_phases(const iga_plan *pl, void *T, void *fuel, StepPhases &sp);
+void step_phases(const iga_plan *pl, void *T, void *fuel, StepPhases &sp,
+                 void *const *work = nullptr);
+// one step of a plan in place (api.cpp); work as for step_phases
+iga_status step_impl(const iga_plan *pl, void *T, void *fuel, hipStream_t s,
+                     const void *src0 = nullptr, const void *src1 = nullptr,
+                     void *const *work = nullptr);
 iga_status check_desc(const iga_plan_desc *d);
 iga_status check_field(const void *p, const char *name);
 

@@ -30,7 +30,7 @@ EXPORTED = ("iga_default_coeffs", "iga_plan_create", "iga_plan_destroy", "iga_pl
             "iga_ensemble_set_assembly_rows", "iga_ensemble_autotune", "iga_step_forced",
             "iga_plan_quadrature_points", "iga_plan_set_column_schedule",
             "iga_plan_set_assembly_stacking", "iga_plan_assembly_stacking",
-            "iga_ensemble_set_assembly_stacking", "iga_last_error")
+            "iga_ensemble_set_assembly_stacking", "iga_step_noalloc", "iga_last_error")
 
 _COEFF_NAMES = ("c_adv", "c_diff", "c_react", "c_nld", "c_ign", "t_ig", "fuel_thr", "t_act",
                 "c_forcing", "c_rad", "fuel_rate")
@@ -87,6 +87,7 @@ def lib() -> ctypes.CDLL:
         L.iga_assemble_rhs.argtypes = [vp, i32, vp, vp, vp, vp, vp]
         L.iga_line_solve.argtypes = [vp, i32, i32, vp, vp]
         L.iga_step.argtypes = [vp, vp, vp, vp]
+        L.iga_step_noalloc.argtypes = [vp, vp, vp, vp]
         L.iga_run.argtypes = [vp, vp, vp, i64, vp]
         L.iga_plan_schedule.argtypes = [vp, i32] + [ctypes.POINTER(i32)] * 4
         L.iga_plan_set_schedule.argtypes = [vp, i32, i32, i32]
@@ -238,6 +239,10 @@ class Plan:
     def step(self, T, fuel, stream=None):
         _check(lib().iga_step(self._h, self._field(T, "T"), self._field(fuel, "fuel"),
                               _stream(stream)), "iga_step")
+
+    def step_noalloc(self, T, fuel, stream=None):
+        _check(lib().iga_step_noalloc(self._h, self._field(T, "T"), self._field(fuel, "fuel"),
+                                      _stream(stream)), "iga_step_noalloc")
 
     def run(self, T, fuel, nsteps, stream=None):
         _check(lib().iga_run(self._h, self._field(T, "T"), self._field(fuel, "fuel"),
