@@ -53,6 +53,8 @@ def parse():
                     help="skip the ensemble workloads (64 uneven members; 16 cubic 2048^2 members)")
     ap.add_argument("--no-paper-meshes", action="store_true",
                     help="skip the FP64 runs on the meshes of the paper's scalability study")
+    ap.add_argument("--no-4096", action="store_true",
+                    help="skip the 4096^2 precision-form workload")
     return ap.parse_args()
 
 
@@ -83,6 +85,48 @@ def time_steps(pl, sc, steps, warmup, torch):
     ev = e0.elapsed_time(e1) / 1e3
     assert torch.isfinite(T).all() and torch.isfinite(F).all()
     return wall, ev, T, F
+
+
+AMB_DT, AMB_DF = 0.01, 1e-5    # near-threshold window of the ignition decision (K, fuel)
+
+
+def sample_grid(sc, n=256):
+    import numpy as np
+    s = (np.arange(n) + 0.5) / n
+    return s * sc.len_x, s * sc.len_y
+
+
+FLIP_K = 0.5    # kelvin: dofs differing by more are counted as affected by a flipped decision
+
+
+def burned_elements(pl, fuel, sc):
+    """Elements whose centre fuel is below 0.1 (the burned area)."""
+    import numpy as np
+    cx = (np.arange(sc.nel_x) + 0.5) * sc.len_x / sc.nel_x
+    cy = (np.arange(sc.nel_y) + 0.5) * sc.len_y / sc.nel_y
+    return int(pl.sample_points(fuel, cx, cy).lt(0.1).sum())
+
+
+def rel_l2(a, b, torch):
+    return float(torch.linalg.vector_norm((a.double() - b.double()).flatten())
+                 / torch.linalg.vector_norm(b.double().flatten()))
+
+
+def precision_errors(pl32, T32, F32, pl64, T64, F64, sc, torch):
+    """FP32+refine against FP64 on the same inputs after the same steps:
+    relative L2 of the T and fuel coefficients and of T at 256^2 cell-centred
+    points (evaluated by the library), the dofs whose T differs by more than
+    0.5 K (ignition decisions taken the other way), the burned elements of
+    each, and the quadrature points of the FP32 state whose ignition decision
+    lies within (0.01 K, 1e-5) of a threshold."""
+    xs, ys = sample_grid(sc)
+    g32 = pl32.sample_points(T32, xs, ys)
+    g64 = pl64.sample_points(T64, xs, ys)
+    return {"rel_l2_T": rel_l2(T32, T64, torch), "rel_l2_fuel": rel_l2(F32, F64, torch),
+            "rel_l2_T_256": rel_l2(g32, g64, torch),
+            "dofs_off_by_0.5K": int((T32.double() - T64).abs().gt(FLIP_K).sum()),
+            "burned_elements": [burned_elements(pl32, F32, sc), burned_elements(pl64, F64, sc)],
+            "near_threshold_points": pl32.count_ambiguous(T32, F32, AMB_DT, AMB_DF)}
 
 
 def kernel_times(pl, sc, reps, torch):
@@ -236,17 +280,51 @@ def ensemble_throughput(scs, steps, torch, iga):
         e1.record(stream)
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
+    launches = ens.launches_per_step
     ok = all(bool(torch.isfinite(t).all()) for t in Ts)
+    ens.close()
+    # the same steps in FP64 (default schedules, untimed) for the precision
+    # error, and the near-threshold points of every FP32 member
+    e64 = iga.Ensemble.from_scenarios(scs, precision="fp64")
+    T64 = [torch.tensor(sc.T0, dtype=torch.float64, device="cuda") for sc in scs]
+    F64 = [torch.tensor(sc.fuel0, dtype=torch.float64, device="cuda") for sc in scs]
+    with torch.cuda.stream(stream):
+        e64.run(T64, F64, steps, stream)   # the FP32 state is `steps` steps from T0
+    torch.cuda.synchronize()
+    e64.close()
+    worst = {"rel_l2_T": 0.0, "rel_l2_fuel": 0.0, "rel_l2_T_256": 0.0}
+    near = flipped = dburn = 0
+    for m, sc in enumerate(scs):
+        worst["rel_l2_T"] = max(worst["rel_l2_T"], rel_l2(Ts[m], T64[m], torch))
+        worst["rel_l2_fuel"] = max(worst["rel_l2_fuel"], rel_l2(Fs[m], F64[m], torch))
+        flipped += int((Ts[m].double() - T64[m]).abs().gt(FLIP_K).sum())
+        pm = iga.Plan.from_scenario(sc, precision="fp32")
+        p64 = iga.Plan.from_scenario(sc, precision="fp64")
+        near += pm.count_ambiguous(Ts[m], Fs[m], AMB_DT, AMB_DF)
+        xs, ys = sample_grid(sc)
+        worst["rel_l2_T_256"] = max(worst["rel_l2_T_256"],
+                                    rel_l2(pm.sample_points(Ts[m], xs, ys),
+                                           p64.sample_points(T64[m], xs, ys), torch))
+        dburn = max(dburn, abs(burned_elements(pm, Fs[m], sc) - burned_elements(p64, F64[m], sc)))
+        pm.close()
+        p64.close()
+    del T64, F64
     dofs = sum(sc.ndof for sc in scs)
     bpd = 60 if scs[0].scheme == "strang" else 52
     out = {"members": len(scs), "dofs": dofs, "steps": steps, "p": scs[0].p,
            "scheme": scs[0].scheme, "value": round(dofs * steps / wall, 1),
            "unit": "DOF-steps/s", "ms_per_step": round(wall / steps * 1e3, 4),
            "event_ms_per_step": round(e0.elapsed_time(e1) / steps, 4),
-           "launches_per_step": ens.launches_per_step,
+           "launches_per_step": launches,
            "step_hbm_frac": round(dofs * steps / wall * bpd / (HBM_PEAK_GBS * 1e9), 4),
-           "finite": ok}
-    ens.close()
+           "finite": ok,
+           "fp32_vs_fp64_after_steps": steps,
+           "worst_member_rel_l2_T": worst["rel_l2_T"],
+           "worst_member_rel_l2_fuel": worst["rel_l2_fuel"],
+           "worst_member_rel_l2_T_256": worst["rel_l2_T_256"],
+           "dofs_off_by_0.5K": flipped,
+           "worst_member_burned_element_difference": dburn,
+           "near_threshold_points": near}
     return out
 
 
@@ -309,7 +387,10 @@ def paper_meshes(torch, iga, inputs):
     return out
 
 
-def cpu_baseline(sc, budget_s):
+def cpu_baseline(sc, budget_s, plans, torch):
+    """The FP64 oracle on the host cores over the first steps of the workload
+    (as many as fit the time budget), and the GPU steppers' states after the
+    same number of steps from the same inputs against the oracle's."""
     import oracle
     d = oracle.desc_from_scenario(sc)
     threads = oracle.get_threads()
@@ -323,6 +404,15 @@ def cpu_baseline(sc, budget_s):
     el = time.perf_counter() - t0
     n_total = n + 1
     el_total = el + one
+    errors = {"steps": n_total}
+    for prec, pl in plans.items():
+        Tg = torch.tensor(sc.T0, dtype=pl.dtype, device="cuda")
+        Fg = torch.tensor(sc.fuel0, dtype=pl.dtype, device="cuda")
+        pl.run(Tg, Fg, n_total)
+        torch.cuda.synchronize()
+        To = torch.from_numpy(T).cuda()
+        Fo = torch.from_numpy(F).cuda()
+        errors[prec] = {"rel_l2_T": rel_l2(Tg, To, torch), "rel_l2_fuel": rel_l2(Fg, Fo, torch)}
     # the same oracle on one core, over the next steps of the run (bounded to
     # a few seconds)
     oracle.set_threads(1)
@@ -338,10 +428,65 @@ def cpu_baseline(sc, budget_s):
         oracle.set_threads(threads)
     return {"value": sc.ndof * n_total / el_total, "unit": "DOF-steps/s", "cores": threads,
             "kind": "oracle",
-            "sample": f"{sc.nel_x}x{sc.nel_y} p={sc.p} Strang-CN FP64, first {n_total} of "
-                      f"{sc.steps} steps ({el_total:.1f} s, {threads} OpenMP threads)",
+            "sample": f"{sc.nel_x}x{sc.nel_y} p={sc.p} Strang-CN FP64: the first {n_total} steps "
+                      f"from the initial state ({el_total:.1f} s on {threads} OpenMP threads)",
             "value_1core": sc.ndof * k1 / el1,
-            "sample_1core": f"steps {n_total + 1}-{n_total + k1} on one OpenMP thread ({el1:.1f} s)"}
+            "sample_1core": f"steps {n_total + 1}-{n_total + k1} on one OpenMP thread ({el1:.1f} s)",
+            "gpu_vs_oracle": errors}
+
+
+def stepper_leg(sc, steps, warmup, args, torch, iga):
+    """FP32+refine and FP64 on one workload: autotuned (or the fixed
+    schedule), graph-replayed timed run, per-kernel event times, and the
+    precision errors between the two final states.  Returns the plans (open)
+    and the measurements."""
+    res, ktimes, plans, finals = {}, {}, {}, {}
+    for prec in ("fp32", "fp64"):
+        pl = iga.Plan.from_scenario(sc, precision=prec)
+        pl.factor()
+        Tt = torch.tensor(sc.T0, dtype=pl.dtype, device="cuda")
+        Ft = torch.tensor(sc.fuel0, dtype=pl.dtype, device="cuda")
+        if args.schedule:
+            apply_schedule(pl, args.schedule)
+        elif args.window_schedule and prec == "fp32":
+            apply_schedule(pl, args.window_schedule, windowed=True)
+        else:
+            pl.autotune(Tt, Ft, reps=10)      # untimed: picks tiles / workgroup widths
+        del Tt, Ft
+        wall, ev, T, F = time_steps(pl, sc, steps, warmup, torch)
+        res[prec] = dict(wall=wall, ev=ev, dofs=sc.ndof * steps / wall,
+                         sched=[dict(pl.schedule(0), **pl.solver(0)),
+                                dict(pl.schedule(1), **pl.solver(1)),
+                                {"assembly_rows": pl.assembly_rows, "assembly_stacked": pl.assembly_stacked}])
+        ktimes[prec] = kernel_times(pl, sc, args.kernel_reps, torch)
+        plans[prec], finals[prec] = pl, (T, F)
+    errs = precision_errors(plans["fp32"], *finals["fp32"], plans["fp64"], *finals["fp64"], sc, torch)
+    errs["after_steps"] = warmup + steps
+    return plans, res, ktimes, errs
+
+
+def config_4096(args, torch, iga, inputs):
+    """The precision form at scale: 4096^2 quadratic, Strang-CN, FP32+refine
+    against FP64 on the same inputs, with the roofline of its dominant
+    kernel and the whole step against HBM."""
+    sc = inputs.regional_strang(seed=1, nel=4096, steps=args.steps)
+    plans, res, ktimes, errs = stepper_leg(sc, args.steps, args.warmup, args, torch, iga)
+    for pl in plans.values():
+        pl.close()
+    kt = ktimes["fp32"]
+    out = {"workload": "regional Strang-CN 4096x4096 quadratic, dt 5e-4",
+           "dofs": sc.ndof, "steps": args.steps,
+           "value": round(res["fp32"]["dofs"], 1), "unit": "DOF-steps/s",
+           "ms_per_step": round(res["fp32"]["wall"] / args.steps * 1e3, 5),
+           "fp64": {"value": round(res["fp64"]["dofs"], 1),
+                    "ms_per_step": round(res["fp64"]["wall"] / args.steps * 1e3, 5),
+                    "kernel_us": {k: round(v * 1e6, 2) for k, v in ktimes["fp64"].items()}},
+           "fp32_over_fp64": round(res["fp32"]["dofs"] / res["fp64"]["dofs"], 3),
+           "step_hbm_frac": round(res["fp32"]["dofs"] * 60 / (HBM_PEAK_GBS * 1e9), 4),
+           "roofline": roofline(kt, sc.p, sc.ndof, sc.nel_x * sc.nel_y, sc.nel_x),
+           "fp32_vs_fp64": errs,
+           "schedules": res["fp32"]["sched"]}
+    return out
 
 
 def main():
@@ -371,27 +516,7 @@ def main():
                           "copy_bytes": 4 * sc.ndof}), flush=True)
         pl.close()
         return
-    res = {}
-    ktimes = {}
-    for prec in ("fp32", "fp64"):
-        pl = iga.Plan.from_scenario(sc, precision=prec)
-        pl.factor()
-        Tt = torch.tensor(sc.T0, dtype=pl.dtype, device="cuda")
-        Ft = torch.tensor(sc.fuel0, dtype=pl.dtype, device="cuda")
-        if args.schedule:
-            apply_schedule(pl, args.schedule)
-        elif args.window_schedule and prec == "fp32":
-            apply_schedule(pl, args.window_schedule, windowed=True)
-        else:
-            pl.autotune(Tt, Ft, reps=10)      # untimed: picks tiles / workgroup widths
-        del Tt, Ft
-        wall, ev, T, F = time_steps(pl, sc, args.steps, args.warmup, torch)
-        res[prec] = dict(wall=wall, ev=ev, dofs=sc.ndof * args.steps / wall,
-                         sched=[dict(pl.schedule(0), **pl.solver(0)),
-                                dict(pl.schedule(1), **pl.solver(1)),
-                                {"assembly_rows": pl.assembly_rows, "assembly_stacked": pl.assembly_stacked}])
-        ktimes[prec] = kernel_times(pl, sc, args.kernel_reps, torch)
-        pl.close()
+    plans, res, ktimes, errs = stepper_leg(sc, args.steps, args.warmup, args, torch, iga)
 
     kt = ktimes["fp32"]
     ndof = sc.ndof
@@ -417,20 +542,28 @@ def main():
                  "ms_per_step": round(res["fp64"]["wall"] / args.steps * 1e3, 5),
                  "kernel_us": {k: round(v * 1e6, 2) for k, v in ktimes["fp64"].items()}},
         "fp32_over_fp64": round(res["fp32"]["dofs"] / res["fp64"]["dofs"], 3),
+        "fp32_vs_fp64": errs,
         # whole step against HBM: 15 fields of 4 B move per DOF-step in the
         # fused minimum of a Strang step
         "step_hbm_frac": round(res["fp32"]["dofs"] * 60 / (HBM_PEAK_GBS * 1e9), 4),
         "roofline": roof,
         "schedules": res["fp32"]["sched"],
     }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(sc, args.cpu_seconds, plans, torch)
+    for pl in plans.values():
+        pl.close()
+    del plans
+    torch.cuda.empty_cache()
+    if not args.no_4096:
+        line["config_4096"] = config_4096(args, torch, iga, inputs)
+        torch.cuda.empty_cache()
     if not args.no_other_schemes:
         line["other_schemes"] = other_schemes(args.nel, args.steps, torch, iga, inputs)
     if not args.no_ensembles:
         line["ensembles"] = ensembles(torch, iga, inputs)
     if not args.no_paper_meshes:
         line["paper_meshes_fp64"] = paper_meshes(torch, iga, inputs)
-    if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(sc, args.cpu_seconds)
     print(json.dumps(line), flush=True)
 
 

@@ -188,6 +188,30 @@ iga_status iga_step_forced(iga_plan *plan, void *T, void *fuel, const void *src0
  * element by element, ascending, written to the host array x. */
 iga_status iga_plan_quadrature_points(const iga_plan *plan, int32_t dir, double *x);
 
+/* Spline values of a field (a coefficient array of the plan, in its
+ * precision) at the nx * ny points (xs[a], ys[b]) of a tensor grid:
+ *   out[a * ny + b] = sum_ij field[i * Ny + j] B_i(xs[a]) B_j(ys[b])
+ * with the plan's tensor-product B-spline basis (Section 3.1), evaluated in
+ * double.  Physical coordinates; points outside [0, len] are clamped to the
+ * domain.  xs, ys and out are device arrays of double owned by the caller
+ * (out must not alias the field).  For comparing fields at sample points
+ * (e.g. 256^2 cell centres) independently of the mesh.  Errors: IGA_EINVAL
+ * for NULL pointers or negative counts. */
+iga_status iga_sample_points(const iga_plan *plan, const void *field, const double *xs, int32_t nx,
+                             const double *ys, int32_t ny, double *out, void *stream);
+
+/* Number of quadrature points (p + 1 Gauss points per direction and
+ * element, as in the assembly) whose ignition decision [T > t_ig and
+ * fuel > fuel_thr] (generic equation at the start of Section 3) lies near a
+ * threshold: |T - t_ig| <= dT with fuel > fuel_thr - dF, or
+ * |fuel - fuel_thr| <= dF with T > t_ig - dT, T and fuel evaluated in double
+ * from the coefficients.  These are the points where evaluations in float
+ * and in double may decide differently.  *count is a device int64 (8-byte
+ * aligned) that the call overwrites.  Errors: IGA_EINVAL for NULL or
+ * misaligned pointers or negative distances. */
+iga_status iga_count_ambiguous(const iga_plan *plan, const void *T, const void *fuel, double dT,
+                               double dF, int64_t *count, void *stream);
+
 /* nsteps steps, in place, replayed from a HIP graph captured on first use for
  * this (T, fuel) pair.  With desc.check_every > 0 the state is tested for
  * NaN/Inf every check_every steps (this synchronises `stream`) and

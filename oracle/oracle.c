@@ -32,6 +32,13 @@
  *  - The fuel is updated once per full step, explicitly from (T^n, fuel^n),
  *    and projected with Mx (x) My (the compute_rhs listing of Section 7).
  *  - p + 1 Gauss points per direction per element.
+ *
+ * Pins (tests/test_oracle_pins.py, tests/test_manufactured.py,
+ * tests/test_ring_of_fire.py) check every function against closed forms,
+ * library routines, dense brute force and invariants of the schemes.
+ * Parity unpinned: the values of c_ign and fuel_rate (the reaction-rate scale
+ * A_r and M/M1 are not given in the paper); with them the full model is
+ * checked only for boundedness and consistency under dt halving.
  */
 #include "oracle.h"
 

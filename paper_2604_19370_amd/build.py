@@ -28,7 +28,7 @@ FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
 
 SOURCES = ["plan.cpp", "api.cpp", "noalloc.cpp", "ensemble.cpp", "factor.hip", "assemble.hip", "sweep.hip",
            "sweep_f1.hip", "sweep_f2.hip", "sweep_f3.hip", "sweep_d1.hip", "sweep_d2.hip",
-           "sweep_d3.hip", "sweep_col.hip"]
+           "sweep_d3.hip", "sweep_col.hip", "sample.hip"]
 
 
 def _compile(src: str) -> tuple[str, float, str]:

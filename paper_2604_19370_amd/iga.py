@@ -12,6 +12,8 @@ import ctypes
 import os
 from typing import Optional
 
+import numpy as np
+
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libiga.so")
 
@@ -30,7 +32,8 @@ EXPORTED = ("iga_default_coeffs", "iga_plan_create", "iga_plan_destroy", "iga_pl
             "iga_ensemble_set_assembly_rows", "iga_ensemble_autotune", "iga_step_forced",
             "iga_plan_quadrature_points", "iga_plan_set_column_schedule",
             "iga_plan_set_assembly_stacking", "iga_plan_assembly_stacking",
-            "iga_ensemble_set_assembly_stacking", "iga_step_noalloc", "iga_last_error")
+            "iga_ensemble_set_assembly_stacking", "iga_step_noalloc", "iga_sample_points",
+            "iga_count_ambiguous", "iga_last_error")
 
 _COEFF_NAMES = ("c_adv", "c_diff", "c_react", "c_nld", "c_ign", "t_ig", "fuel_thr", "t_act",
                 "c_forcing", "c_rad", "fuel_rate")
@@ -88,6 +91,8 @@ def lib() -> ctypes.CDLL:
         L.iga_line_solve.argtypes = [vp, i32, i32, vp, vp]
         L.iga_step.argtypes = [vp, vp, vp, vp]
         L.iga_step_noalloc.argtypes = [vp, vp, vp, vp]
+        L.iga_sample_points.argtypes = [vp, vp, vp, i32, vp, i32, vp, vp]
+        L.iga_count_ambiguous.argtypes = [vp, vp, vp, ctypes.c_double, ctypes.c_double, vp, vp]
         L.iga_run.argtypes = [vp, vp, vp, i64, vp]
         L.iga_plan_schedule.argtypes = [vp, i32] + [ctypes.POINTER(i32)] * 4
         L.iga_plan_set_schedule.argtypes = [vp, i32, i32, i32]
@@ -243,6 +248,29 @@ class Plan:
     def step_noalloc(self, T, fuel, stream=None):
         _check(lib().iga_step_noalloc(self._h, self._field(T, "T"), self._field(fuel, "fuel"),
                                       _stream(stream)), "iga_step_noalloc")
+
+    def sample_points(self, field, xs, ys, stream=None):
+        """Spline values of `field` at the grid (xs[a], ys[b]) (physical
+        coordinates, host sequences); returns a (len(xs), len(ys)) float64
+        device tensor."""
+        import torch
+        x = torch.as_tensor(np.asarray(xs, dtype=np.float64)).cuda()
+        y = torch.as_tensor(np.asarray(ys, dtype=np.float64)).cuda()
+        out = torch.empty((x.numel(), y.numel()), dtype=torch.float64, device="cuda")
+        _check(lib().iga_sample_points(self._h, self._field(field, "field"), _ptr(x), x.numel(),
+                                       _ptr(y), y.numel(), _ptr(out), _stream(stream)),
+               "iga_sample_points")
+        return out
+
+    def count_ambiguous(self, T, fuel, dT, dF, stream=None) -> int:
+        """Quadrature points whose ignition decision lies within (dT, dF) of
+        its thresholds (synchronises)."""
+        import torch
+        c = torch.empty(1, dtype=torch.int64, device="cuda")
+        _check(lib().iga_count_ambiguous(self._h, self._field(T, "T"), self._field(fuel, "fuel"),
+                                         float(dT), float(dF), _ptr(c), _stream(stream)),
+               "iga_count_ambiguous")
+        return int(c.item())
 
     def run(self, T, fuel, nsteps, stream=None):
         _check(lib().iga_run(self._h, self._field(T, "T"), self._field(fuel, "fuel"),

@@ -23,14 +23,17 @@ arithmetic throughout:
                perturbation of the same size).
 
 For each variant against ref: relative L2 of the T and fuel coefficients,
-relative L2 of T at 256^2 cell-centred points, the max |dT|, and the burned
-fractions (element-centre fuel < 0.1).  The 4096^2 case also stores the
+relative L2 of T at 256^2 cell-centred points, the max |dT|, the dofs whose
+T differs by more than 0.5 K (taken as affected by a flipped decision) and
+the relative L2 away from them, and the burned fractions (element-centre
+fuel < 0.1).  The 4096^2 case also stores the
 oracle's own temperature at the 256^2 points after 200 steps
 (oracle_regional4096_200steps_256.npz).
 
 Usage:  python tests/golden/make_fp32_spread.py CASE [CASE ...]
 Cases are merged into the existing JSON file.  Costs on 8 host threads:
-regional256 ~5 s, regional1024 ~8 min (all variants), regional4096 ~40 min.
+regional256 ~10 s, regional1024 ~8 min (all variants), mixed_members ~14 min,
+cubic20 ~10 min, regional4096 ~40 min.
 """
 from __future__ import annotations
 
@@ -46,7 +49,9 @@ ROOT = os.path.dirname(os.path.dirname(HERE))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
+sys.path.insert(0, os.path.dirname(HERE))
 import oracle  # noqa: E402
+import parity_util as pu  # noqa: E402
 from paper_2604_19370_amd import inputs  # noqa: E402
 
 OUT = os.path.join(HERE, "fp32_spread.json")
@@ -60,23 +65,30 @@ def f32(a):
     return a.astype(np.float32).astype(np.float64)
 
 
-def run_variant(od, T0, F0, steps, kind, seed=0):
-    if kind == "ref":
-        return oracle.run(od, T0, F0, steps)
-    if kind == "round_init":
-        return oracle.run(od, f32(T0), f32(F0), steps)
+def run_variant(od, T0, F0, steps, kind, seed=0, checkpoints=()):
+    """The variant's state after `steps` steps, and at each checkpoint."""
+    at = {}
+    if kind in ("ref", "round_init"):
+        T, F = (T0, F0) if kind == "ref" else (f32(T0), f32(F0))
+        done = 0
+        for k in sorted(set(checkpoints) | {steps}):
+            T, F = oracle.run(od, T, F, k - done)
+            done = k
+            at[k] = (T, F)
+        return at[steps], at
     rng = np.random.default_rng(seed)
-    T, F = f32(T0), f32(F0)
-    if kind.startswith("perturb"):
-        T, F = T0.copy(), F0.copy()
-    for _ in range(steps):
+    T, F = (f32(T0), f32(F0)) if kind == "round_each" else (T0.copy(), F0.copy())
+    for k in range(1, steps + 1):
         T, F = oracle.step(od, T, F)
         if kind == "round_each":
             T, F = f32(T), f32(F)
         else:
             T = T * (1.0 + rng.uniform(-1, 1, T.shape) * 2.0 ** -24)
             F = F * (1.0 + rng.uniform(-1, 1, F.shape) * 2.0 ** -24)
-    return T, F
+        if k in checkpoints:
+            at[k] = (T, F)
+    at[steps] = (T, F)
+    return (T, F), at
 
 
 def compare(od, sc, ref, var):
@@ -84,20 +96,24 @@ def compare(od, sc, ref, var):
     ys = (np.arange(256) + 0.5) / 256 * sc.len_y
     gr = oracle.eval_grid(od, ref[0], xs, ys)
     gv = oracle.eval_grid(od, var[0], xs, ys)
+    fl = pu.flip_report(var[0], ref[0])
     return {
         "rel_T": rel(var[0], ref[0]),
         "rel_fuel": rel(var[1], ref[1]),
         "rel_T_256": rel(gv, gr),
         "max_abs_T": float(np.abs(var[0] - ref[0]).max()),
+        "flipped_dofs": fl["flipped"],
+        "flipped_frac": fl["flipped_frac"],
+        "rel_T_away_from_flips": fl["out_rel"],
         "burned_ref": oracle.burned_fraction(od, ref[1]),
         "burned_var": oracle.burned_fraction(od, var[1]),
     }
 
 
-def spread(sc, variants, coeffs=None, save_grid=None):
+def spread(sc, variants, coeffs=None, save_grid=None, checkpoints=()):
     od = oracle.desc_from_scenario(sc, coeffs=coeffs)
     t0 = time.time()
-    ref = run_variant(od, sc.T0, sc.fuel0, sc.steps, "ref")
+    ref, ref_at = run_variant(od, sc.T0, sc.fuel0, sc.steps, "ref", checkpoints=checkpoints)
     out = {"steps": sc.steps, "dofs": int(sc.T0.size)}
     if save_grid:
         # the oracle's temperature at 256^2 cell-centred points after the run,
@@ -109,9 +125,21 @@ def spread(sc, variants, coeffs=None, save_grid=None):
                             burned=oracle.burned_fraction(od, ref[1]), steps=sc.steps)
     for v in variants:
         kind, seed = (v.split("_")[0], int(v.split("_")[1])) if v.startswith("perturb") else (v, 0)
-        var = run_variant(od, sc.T0, sc.fuel0, sc.steps, kind, seed)
+        var, var_at = run_variant(od, sc.T0, sc.fuel0, sc.steps, kind, seed, checkpoints)
         out[v] = compare(od, sc, ref, var)
+        if checkpoints:
+            out[v]["at_step"] = {str(k): compare(od, sc, ref_at[k], var_at[k]) for k in checkpoints}
         print(f"  {v}: {out[v]}  ({time.time() - t0:.0f} s)", flush=True)
+    return out
+
+
+def cubic_members(scheme, members, steps):
+    scs = inputs.cubic_ensemble(max(members) + 1, scheme=scheme)
+    out = {}
+    for m in members:
+        sc = scs[m]
+        sc.steps = steps
+        out[f"member{m}"] = spread(sc, ["round_each"])
     return out
 
 
@@ -127,7 +155,10 @@ CASES = {
                               ["round_each"], coeffs={"c_ign": 0.0})},
     "regional4096": lambda: {
         "ignition": spread(inputs.regional_strang(seed=1, nel=4096, steps=200), ["round_each"],
-                           save_grid="oracle_regional4096_200steps_256.npz")},
+                           save_grid="oracle_regional4096_200steps_256.npz", checkpoints=(20,))},
+    # members 0 and 15 of the 16-member cubic 2048^2 ensembles (seeds 2000,
+    # 2015), 20 steps of each scheme
+    "cubic20": lambda: {s: cubic_members(s, (0, 15), 20) for s in ("strang", "pr")},
     # members 0-3 of the 64-member uneven ensemble (seeds 1000-1003), 300 steps
     "mixed_members": lambda: {
         f"member{m}": spread(inputs.mixed_ensemble(4)[m], ["round_each"]) for m in range(4)},

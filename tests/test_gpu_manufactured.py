@@ -12,6 +12,7 @@ import numpy as np
 import pytest
 
 import oracle
+import parity_util as pu
 from paper_2604_19370_amd import iga, inputs, study
 
 pytestmark = pytest.mark.gpu
@@ -49,18 +50,20 @@ def test_forced_steps_random_source(p, scheme, precision):
     np.testing.assert_allclose(xq, oracle.quad_points(sc.nel_x, p, sc.len_x), rtol=0, atol=1e-13)
     np.testing.assert_allclose(yq, oracle.quad_points(sc.nel_y, p, sc.len_y), rtol=0, atol=1e-13)
     rng = np.random.default_rng(7 * p)
-    T, F = dev(sc.T0, pl.dtype), dev(sc.fuel0, pl.dtype)
     tol = 1e-12 if precision == "fp64" else 1e-6
+    Th, Fh = sc.T0, sc.fuel0    # the oracle's trajectory; each GPU step starts from it
     for k in range(3):
         s0 = rng.normal(0.0, 500.0, (xq.size, yq.size))
         s1 = rng.normal(0.0, 500.0, (xq.size, yq.size))
         if precision == "fp32":
             s0, s1 = s0.astype(np.float32).astype(np.float64), s1.astype(np.float32).astype(np.float64)
-        Tp, Fp = host(T), host(F)
+        Tp, Fp = (pu.f32(Th), pu.f32(Fh)) if precision == "fp32" else (Th, Fh)
+        T, F = dev(Tp, pl.dtype), dev(Fp, pl.dtype)
         pl.step_forced(T, F, dev(s0, pl.dtype), None if scheme == "explicit" else dev(s1, pl.dtype))
         To, Fo = oracle.step_forced(od, Tp, Fp, *oracle_srcs(scheme, s0, s1))
         eT, eF = rel(host(T), To), rel(host(F), Fo)
         assert eT < tol and eF < tol, (k, eT, eF)
+        Th, Fh = oracle.step_forced(od, Th, Fh, *oracle_srcs(scheme, s0, s1))
     pl.close()
 
 
@@ -74,18 +77,20 @@ def test_forced_steps_manufactured_source(scheme, precision):
     pl.factor()
     od = oracle.desc_from_scenario(sc, coeffs=co)
     X, Y = pl.quadrature_points(0)[:, None], pl.quadrature_points(1)[None, :]
-    T, F = dev(sc.T0, pl.dtype), dev(sc.fuel0, pl.dtype)
     tol = 1e-12 if precision == "fp64" else 1e-6
+    Th, Fh = sc.T0, sc.fuel0    # the oracle's trajectory; each GPU step starts from it
     for n in range(4):
         t = n * sc.dt
         s0, s1 = m.source(X, Y, t), m.source(X, Y, t + 0.5 * sc.dt)
         if precision == "fp32":
             s0, s1 = s0.astype(np.float32).astype(np.float64), s1.astype(np.float32).astype(np.float64)
-        Tp, Fp = host(T), host(F)
+        Tp, Fp = (pu.f32(Th), pu.f32(Fh)) if precision == "fp32" else (Th, Fh)
+        T, F = dev(Tp, pl.dtype), dev(Fp, pl.dtype)
         pl.step_forced(T, F, dev(s0, pl.dtype), None if scheme == "explicit" else dev(s1, pl.dtype))
         To, _ = oracle.step_forced(od, Tp, Fp, *oracle_srcs(scheme, s0, s1))
         assert rel(host(T), To) < tol, n
         assert np.all(host(F) == 0.0)
+        Th, Fh = oracle.step_forced(od, Th, Fh, *oracle_srcs(scheme, s0, s1))
     pl.close()
 
 

@@ -9,6 +9,7 @@ import numpy as np
 import pytest
 
 import oracle
+import parity_util as pu
 from paper_2604_19370_amd import iga, inputs
 
 pytestmark = pytest.mark.gpu
@@ -31,6 +32,39 @@ def host(t):
 
 def rel(a, b):
     return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def upload(t, a):
+    torch.cuda.synchronize()
+    t.copy_(torch.from_numpy(np.ascontiguousarray(a)).to(t.dtype))
+    torch.cuda.synchronize()
+
+
+def per_step_parity(pl, od, sc, nsteps, precision, step=None):
+    """nsteps steps of the oracle's trajectory from (T0, fuel0); each one is
+    also taken by the plan from the oracle's state (float-rounded for FP32)
+    and compared with the oracle's step from that same state: relative L2
+    and element by element (parity_util)."""
+    fp32 = precision == "fp32"
+    t, f = dev(sc.T0, fp32), dev(sc.fuel0, fp32)
+    Th, Fh = sc.T0, sc.fuel0
+    worst = 0.0
+    for k in range(nsteps):
+        Tin, Fin = (pu.f32(Th), pu.f32(Fh)) if fp32 else (Th, Fh)
+        upload(t, Tin)
+        upload(f, Fin)
+        (step or pl.step)(t, f)
+        if fp32:
+            r = pu.step_report_fp32(od, sc.p, Tin, Fin, host(t), host(f))
+            pu.assert_step_fp32(r, TOL32, what=k)
+            worst = max(worst, r["T_rel"], r["fuel_rel"])
+            Th, Fh = oracle.step(od, Th, Fh)
+        else:
+            To, Fo = oracle.step(od, Th, Fh)
+            worst = max(worst, pu.assert_close_fp64(host(t), To, TOL64, what=("T", k)),
+                        pu.assert_close_fp64(host(f), Fo, TOL64, what=("fuel", k)))
+            Th, Fh = To, Fo
+    return worst
 
 
 def plan_and_oracle(sc, precision="fp64", coeffs=None):
@@ -196,13 +230,7 @@ def test_steps_fp32_column_schedule(nx, ny, p, scheme, mm):
     sc = inputs.small_case(500 + nx, nx, ny, p, scheme, dt=2e-3)
     pl, od = plan_and_oracle(sc, "fp32")
     pl.set_column_schedule(mm)
-    t, f = dev(sc.T0, True), dev(sc.fuel0, True)
-    for k in range(3):
-        T0, F0 = host(t), host(f)
-        T, F = oracle.step(od, T0, F0)
-        pl.step(t, f)
-        assert rel(host(t), T) < TOL32, k
-        assert rel(host(f), F) < TOL32, k
+    per_step_parity(pl, od, sc, 3, "fp32")
     t2, f2 = dev(sc.T0, True), dev(sc.fuel0, True)
     for _ in range(3):
         pl.step(t2, f2)
@@ -307,13 +335,15 @@ def test_steps_fp64(nx, ny, p, scheme):
     print(f"steps fp64 {nx}x{ny} p{p} {scheme}", flush=True)
     sc = inputs.small_case(300 + nx, nx, ny, p, scheme, dt=2e-3)
     pl, od = plan_and_oracle(sc)
+    per_step_parity(pl, od, sc, 4, "fp64")
+    # and four steps in a row on the device against four oracle steps
     T, F = sc.T0.copy(), sc.fuel0.copy()
     t, f = dev(T), dev(F)
     for k in range(4):
         T, F = oracle.step(od, T, F)
         pl.step(t, f)
-        assert rel(host(t), T) < TOL64, k
-        assert rel(host(f), F) < TOL64, k
+        pu.assert_close_fp64(host(t), T, TOL64, what=("T", k))
+        pu.assert_close_fp64(host(f), F, TOL64, what=("fuel", k))
 
 
 @pytest.mark.parametrize("nx,ny,p,scheme", CASES)
@@ -350,29 +380,15 @@ def test_steps_fp32_refine(nx, ny, p, scheme):
     print(f"steps fp32 {nx}x{ny} p{p} {scheme}", flush=True)
     sc = inputs.small_case(400 + nx, nx, ny, p, scheme, dt=2e-3)
     pl, od = plan_and_oracle(sc, "fp32")
-    T, F = sc.T0.copy(), sc.fuel0.copy()
-    t, f = dev(T, True), dev(F, True)
-    for k in range(3):
-        T0 = host(t)
-        F0 = host(f)
-        T, F = oracle.step(od, T0, F0)   # one step from the GPU state: per-step error
-        pl.step(t, f)
-        assert rel(host(t), T) < TOL32, k
-        assert rel(host(f), F) < TOL32, k
+    per_step_parity(pl, od, sc, 3, "fp32")
 
 
 def test_plain_pr_64_twenty_steps_fp64():
     """64x64 quadratic, PR, dt 1e-3, 20 steps: per-step parity with the oracle."""
     sc = inputs.plain_pr_64(0)
     pl, od = plan_and_oracle(sc)
-    T, F = sc.T0.copy(), sc.fuel0.copy()
-    t, f = dev(T), dev(F)
-    for k in range(sc.steps):
-        Tprev, Fprev = host(t), host(f)
-        T, F = oracle.step(od, Tprev, Fprev)
-        pl.step(t, f)
-        assert rel(host(t), T) < TOL64, k
-        assert rel(host(f), F) < TOL64, k
+    worst = per_step_parity(pl, od, sc, sc.steps, "fp64")
+    print(f"worst per-step rel L2 over {sc.steps} steps: {worst:.3e}", flush=True)
 
 
 @pytest.mark.parametrize("precision,stacked", [("fp64", False), ("fp64", True),
@@ -471,6 +487,4 @@ def test_autotune_then_step_parity(precision, tol):
     sched = [pl.schedule(0), pl.schedule(1)]
     assert all(s["lines"] * s["waves_per_line"] <= 16 for s in sched)
     assert 0 < sched[0]["table_rows"] < 80            # interior rows merged
-    T, F = oracle.step(od, host(t), host(f))
-    pl.step(t, f)
-    assert rel(host(t), T) < tol and rel(host(f), F) < tol
+    per_step_parity(pl, od, sc, 2, precision)
