@@ -41,12 +41,17 @@ def parse():
     ap.add_argument("--kernels-only", action="store_true",
                     help="only launch each kernel of the FP32 step --kernel-reps times, plus a "
                          "copy kernel of known size (for profiler runs)")
+    ap.add_argument("--tune", action="store_true",
+                    help="with --kernels-only: autotune first (as the timed runs do)")
     ap.add_argument("--schedule", type=str, default=None,
                     help="fixed exact line-solve schedule 'xlines,xwpl,ylines,ywpl,asmrows' "
                          "instead of autotuning")
     ap.add_argument("--window-schedule", type=str, default=None,
                     help="fixed windowed line-solve schedule 'xlines,xrows,ylines,yrows,asmrows' "
                          "(rows per lane) instead of autotuning")
+    ap.add_argument("--column-schedule", type=int, default=0,
+                    help="with --kernels-only: column-wave x-line solves with this many rows "
+                         "per chunk (16 or 32), after --window-schedule")
     ap.add_argument("--no-other-schemes", action="store_true",
                     help="skip the PR and explicit-scheme lines at the same size")
     ap.add_argument("--no-ensembles", action="store_true",
@@ -178,13 +183,16 @@ def assembly_flops(p, fuel):
     return 2 * fma + pointwise * q * q
 
 
-KERNEL_FAMILY = {"assemble_s1_fuel": "k_assemble<float,p=2,fuel=true>",
-                 "assemble_s3": "k_assemble<float,p=2,fuel=false>",
-                 "sweep_x_A": "k_wsweep<float,p=2,x-lines>",
-                 "sweep_y_M": "k_wsweep<float,p=2,y-lines>",
-                 "sweep_y_cn": "k_wsweep<float,p=2,y-lines>"}
+# counter-summary entries per kernel of the step (the first one present is
+# used: x-lines run windowed or, where the autotuner picks them, by column waves)
+KERNEL_FAMILY = {"assemble_s1_fuel": ("k_assemble<float,p=2,fuel=true>",),
+                 "assemble_s3": ("k_assemble<float,p=2,fuel=false>",),
+                 "sweep_x_A": ("k_wsweep<float,p=2,x-lines>", "k_csweep<2,32>", "k_csweep<2,16>"),
+                 "sweep_y_M": ("k_wsweep<float,p=2,y-lines>",),
+                 "sweep_y_cn": ("k_wsweep<float,p=2,y-lines>",)}
 SOURCES = {"k_assemble": ("assemble.hip",),
-           "k_wsweep": ("sweep_win.h", "sweep_kernels.h", "sweep.hip")}
+           "k_wsweep": ("sweep_win.h", "sweep_kernels.h", "sweep.hip"),
+           "k_csweep": ("sweep_col.h", "sweep_col.hip")}
 
 
 def measured_traffic(kernel, nel):
@@ -198,10 +206,11 @@ def measured_traffic(kernel, nel):
     m = re.search(r"```json\n(.*?)\n```", open(path).read(), re.S)
     if not m:
         return None
-    fam = KERNEL_FAMILY[kernel]
-    ent = json.loads(m.group(1))["kernels"].get(fam)
-    if ent is None:
+    table = json.loads(m.group(1))["kernels"]
+    fam = next((f for f in KERNEL_FAMILY[kernel] if f in table), None)
+    if fam is None:
         return None
+    ent = table[fam]
     h = hashlib.sha256()
     for f in SOURCES[fam.split("<")[0]]:
         h.update(open(os.path.join(ROOT, "paper_2604_19370_amd", "csrc", f), "rb").read())
@@ -507,6 +516,13 @@ def main():
             apply_schedule(pl, args.schedule)
         if args.window_schedule:
             apply_schedule(pl, args.window_schedule, windowed=True)
+        if args.column_schedule:
+            pl.set_column_schedule(args.column_schedule)
+        if args.tune:
+            Tt = torch.tensor(sc.T0, dtype=pl.dtype, device="cuda")
+            Ft = torch.tensor(sc.fuel0, dtype=pl.dtype, device="cuda")
+            pl.autotune(Tt, Ft, reps=10)
+            del Tt, Ft
         kt = kernel_times(pl, sc, args.kernel_reps, torch)
         copy_kernel(4 * sc.ndof, args.kernel_reps, torch)
         print(json.dumps({"kernel_us": {k: round(v * 1e6, 2) for k, v in kt.items()},
