@@ -45,6 +45,14 @@
 // (B-splines are non-negative and sum to one), so where no coefficient of any
 // element of the wavefront's row exceeds T_ig (less a rounding margin) the
 // Arrhenius term is zero and the fuel terms that only it feeds are skipped.
+// In increment form (FP32 plans) an element whose coefficients all equal the
+// ambient fixed point (where c_react T + c_forcing - c_rad T^4 = 0) has no
+// gradient and no net source, so it contributes nothing; where that holds for
+// every element of the wavefront's row, the row's pointwise terms and test
+// contractions are skipped too.
+#include <cmath>
+#include <limits>
+
 #include "dpp.h"
 #include "iga_internal.h"
 
@@ -64,6 +72,10 @@ template <typename T> struct AsmParams {
     T cs_w[4], frc_w[4], rad_w[4], nld_w[4], dx_w[4], dy_w[4], ign_w[4], cf_w[4], rate_w[4];
     T cx, cy, bca;      // bca = beta c_adv
     T t_ig, t_skip, fthr, t_act;
+    // increment form: an element whose coefficients all equal t_fix (the
+    // ambient fixed point) contributes nothing, and is skipped when amb != 0
+    T t_fix;
+    int amb;
     int fuel_all;       // fuel right-hand side nonzero without ignition (direct form)
     int nel_x, nel_y, Nx, Ny, rows, nstrips, ntiles, ngroups;   // rows: dof rows per tile
     int stack;   // tiles of a workgroup share halos (else each evaluates its own);
@@ -132,9 +144,10 @@ __device__ __forceinline__ void assemble_body(const AsmParams<T> &a, const int s
             }
         }
     };
-    // y half of the sum factorisation of one fetched row, and the largest
-    // coefficient of the row within the lane's element
-    auto ytransform = [&](T c0, T c1, T f0, T f1, T(&v)[Q], T(&d)[Q], T(&f)[Q], T &mx) {
+    // y half of the sum factorisation of one fetched row, the largest
+    // coefficient of the row within the lane's element, and whether all of
+    // them equal the ambient fixed point
+    auto ytransform = [&](T c0, T c1, T f0, T f1, T(&v)[Q], T(&d)[Q], T(&f)[Q], T &mx, bool &am) {
         T cb[Q], fb[Q];
         cb[0] = c0;
         fb[0] = f0;
@@ -149,8 +162,12 @@ __device__ __forceinline__ void assemble_body(const AsmParams<T> &a, const int s
             fb[3] = lane_ahead<3>(f0, f1, lane);
         }
         mx = cb[0];
+        am = cb[0] == a.t_fix;
 #pragma unroll
-        for (int b = 1; b < Q; ++b) mx = fmax(mx, cb[b]);
+        for (int b = 1; b < Q; ++b) {
+            mx = fmax(mx, cb[b]);
+            am = am && cb[b] == a.t_fix;
+        }
 #pragma unroll
         for (int q = 0; q < Q; ++q) {
             T sv = 0, sd = 0, sf = 0;
@@ -170,6 +187,7 @@ __device__ __forceinline__ void assemble_body(const AsmParams<T> &a, const int s
     const int K = X1 - E0 + (tail ? P : 0);   // marching steps
     // rings indexed by (step + i) mod Q
     T tv[Q][Q], td[Q][Q], tf[Q][Q], rmx[Q];
+    bool ram[Q];
     T acc0[Q][Q], acc1[Q][Q], accf[Q][Q];
     T pc0[Q], pc1[Q], pf0[Q], pf1[Q];
 #pragma unroll
@@ -181,7 +199,7 @@ __device__ __forceinline__ void assemble_body(const AsmParams<T> &a, const int s
     for (int s = 0; s < P; ++s) {
         T c0, c1, f0, f1;
         fetch(E0 + s, c0, c1, f0, f1);
-        ytransform(c0, c1, f0, f1, tv[s], td[s], tf[s], rmx[s]);
+        ytransform(c0, c1, f0, f1, tv[s], td[s], tf[s], rmx[s], ram[s]);
     }
     // pending loads: step k consumes row E0 + P + k from slot k mod Q
 #pragma unroll
@@ -192,9 +210,17 @@ __device__ __forceinline__ void assemble_body(const AsmParams<T> &a, const int s
         constexpr int ph = decltype(phase)::value;
         constexpr int snew = (ph + P) % Q;   // slot of the new coefficient row / dof row ex+P
         const int ex = E0 + k;
-        ytransform(pc0[ph], pc1[ph], pf0[ph], pf1[ph], tv[snew], td[snew], tf[snew], rmx[snew]);
+        ytransform(pc0[ph], pc1[ph], pf0[ph], pf1[ph], tv[snew], td[snew], tf[snew], rmx[snew],
+                   ram[snew]);
         fetch(ex + P + Q, pc0[ph], pc1[ph], pf0[ph], pf1[ph]);
-        if (ex >= 0 && ex < a.nel_x && ex < X1) {
+        // an element whose coefficients all sit at the ambient fixed point
+        // has no gradient, no net source and no ignition: in increment form
+        // it contributes exactly nothing (the skip is wavefront-uniform)
+        bool eam = ram[0];
+#pragma unroll
+        for (int s = 1; s < Q; ++s) eam = eam && ram[s];
+        const bool quiet = !SRC && a.amb && __all(!eyok || eam);
+        if (ex >= 0 && ex < a.nel_x && ex < X1 && !quiet) {
             const int e2 = (ex >= P && ex < a.nel_x - P) ? P : ex;   // interior tables coincide
             const T *bxe = a.bx + (size_t)e2 * 2 * Q * Q;
             T bxv[Q][Q], bxd[Q][Q], kyw[Q];
@@ -431,6 +457,29 @@ void k_assemble_batch(const AsmParams<T> *__restrict__ prms, const int2 *__restr
     assemble_group<T, P, FUEL, false, STK>(prms[wi.x], wi.y);
 }
 
+// The ambient fixed point: the temperature c > 0 at which the source of a
+// constant field vanishes, c_react c + c_forcing - c_rad c^4 = 0 (the
+// ambient temperature of the generic equation at the start of Section 3;
+// 300 K with the default coefficients).  Newton from the radiative root.
+static bool ambient_fixed_point(const iga_coeffs &c, double &out)
+{
+    auto g = [&](double t) { return c.c_react * t + c.c_forcing - c.c_rad * t * t * t * t; };
+    double t;
+    if (c.c_rad > 0 && c.c_forcing > 0) t = std::pow(c.c_forcing / c.c_rad, 0.25);
+    else if (c.c_rad == 0 && c.c_react != 0) t = -c.c_forcing / c.c_react;
+    else return false;
+    for (int it = 0; it < 60 && std::isfinite(t) && t > 0; ++it) {
+        const double d = c.c_react - 4.0 * c.c_rad * t * t * t;
+        if (d == 0) return false;
+        const double step = g(t) / d;
+        t -= step;
+        if (std::fabs(step) <= 1e-15 * std::fabs(t)) break;
+    }
+    if (!std::isfinite(t) || !(t > 0)) return false;
+    out = t;
+    return true;
+}
+
 template <typename T>
 static void make_params(const iga_plan *pl, int substep, const void *S, const void *F, void *R,
                         void *RF, AsmParams<T> &a, const void *src = nullptr)
@@ -504,6 +553,23 @@ static void make_params(const iga_plan *pl, int substep, const void *S, const vo
     a.t_skip = (T)(d.c.t_ig - 1e-4 * std::fabs(d.c.t_ig));
     a.fthr = (T)d.c.fuel_thr;
     a.t_act = (T)d.c.t_act;
+    // Increment form, no sampled source: elements whose coefficients all equal
+    // the fixed point in the state's precision are skipped, provided the
+    // source left at that rounded value, over a step, is far below the
+    // state's resolution there (and the point is below the ignition cut).
+    a.amb = 0;
+    a.t_fix = T(0);
+    double tfix;
+    if (pl->delta && !src && ambient_fixed_point(d.c, tfix)) {
+        const T tf = (T)tfix;
+        const double t = (double)tf;
+        const double gres = d.c.c_react * t + d.c.c_forcing - d.c.c_rad * t * t * t * t;
+        const double ulp = std::ldexp(t, -std::numeric_limits<T>::digits);
+        if (std::fabs(gres) * d.dt <= 1e-3 * ulp && tf < a.t_skip) {
+            a.amb = 1;
+            a.t_fix = tf;
+        }
+    }
     a.fuel_all = cf != 0.0;
     a.nel_x = d.nel_x;
     a.nel_y = d.nel_y;

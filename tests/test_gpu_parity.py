@@ -375,6 +375,36 @@ def test_assemble_fp32_increment_form(nx, ny, p, scheme):
         assert np.abs(host(rf) - RFd).max() < 2e-6 * max(np.abs(RF).max(), 1e-30)
 
 
+@pytest.mark.parametrize("p", [1, 2, 3])
+@pytest.mark.parametrize("scheme,substep", [("strang", 0), ("strang", 2), ("pr", 1), ("explicit", 0)])
+def test_assemble_fp32_ambient_elements(p, scheme, substep):
+    """In increment form an element whose coefficients all sit at the ambient
+    fixed point (300 K with these coefficients) contributes nothing, and
+    wavefront rows made only of such elements are skipped.  A field at
+    exactly 300 K except for two hot blocks: the FP32 right-hand sides match
+    the oracle's increment form element by element (2e-6 of the largest
+    increment), and rows far from the blocks are exactly zero (the skip ran;
+    a float evaluation of them would leave rounding residue)."""
+    nx, ny = 150, 140
+    sc = inputs.small_case(900 + p, nx, ny, p, scheme)
+    pl, od = plan_and_oracle(sc, "fp32")
+    T = np.full((nx + p, ny + p), 300.0)
+    T[20:40, 30:50] = 1000.0       # burning block (ignites)
+    T[90:100, 70:120] = 650.0      # warm block (below T_ig)
+    F = sc.fuel0.astype(np.float32).astype(np.float64)
+    R, RF = oracle.assemble(od, substep, T, F, with_fuel=True)
+    dR, dRF = pu.increment_rhs(od, substep, R, RF, T, F)
+    t, f = dev(T, True), dev(F, True)
+    r, rf = torch.zeros_like(t), torch.zeros_like(t)
+    pl.assemble_rhs(substep, t, f, r, rf)
+    g, gf = host(r), host(rf)
+    assert np.abs(g - dR).max() <= 2e-6 * np.abs(dR).max()
+    assert np.abs(gf - dRF).max() <= 2e-6 * max(np.abs(dRF).max(), 1e-30)
+    # rows 60..80 touch only ambient elements across the whole width
+    assert np.all(g[60:80] == 0.0) and np.all(gf[60:80] == 0.0)
+    pl.close()
+
+
 @pytest.mark.parametrize("nx,ny,p,scheme", CASES)
 def test_steps_fp32_refine(nx, ny, p, scheme):
     print(f"steps fp32 {nx}x{ny} p{p} {scheme}", flush=True)
