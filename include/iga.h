@@ -266,6 +266,20 @@ iga_status iga_plan_set_schedule(iga_plan *plan, int32_t dir, int32_t lines,
 iga_status iga_plan_set_window_schedule(iga_plan *plan, int32_t dir, int32_t lines,
                                         int32_t rows_per_lane);
 
+/* LDS form of the windowed solves of direction dir: buffers = 2 keeps two
+ * line buffers per line (lanes publish into one while others still read the
+ * other); 1 keeps one (a barrier before every overwrite), and a job with two
+ * operators (Strang S1 with S2) stages the second operator's tables over the
+ * first's once its solve is done; 0 (the default) picks 1 where that lets
+ * more workgroups share a compute unit, else 2.  Both forms compute the same
+ * values in the same order (bitwise equal results).  Applies to the current
+ * and later windowed schedules of the direction; IGA_EINVAL for other
+ * values.  iga_plan_window_buffers returns the form in use (1 or 2), 0 if
+ * direction dir is not solved by windowed solves, -1 for a NULL plan or a
+ * bad dir. */
+iga_status iga_plan_set_window_buffers(iga_plan *plan, int32_t dir, int32_t buffers);
+int32_t iga_plan_window_buffers(const iga_plan *plan, int32_t dir);
+
 /* Column waves for the x-lines of an FP32 plan: one line per lane, 64
  * adjacent lines per wavefront, each wavefront a chunk of rows_per_chunk rows
  * (16 or 32; 0: 32) with its own warm-up rows on both sides, so every access

@@ -419,6 +419,28 @@ iga_status iga_plan_set_window_schedule(iga_plan *plan, int32_t dir, int32_t lin
     return IGA_OK;
 }
 
+iga_status iga_plan_set_window_buffers(iga_plan *plan, int32_t dir, int32_t buffers)
+{
+    if (!plan) return fail(IGA_EINVAL, "plan is NULL");
+    if (dir != 0 && dir != 1) return fail(IGA_EINVAL, "dir must be 0 or 1");
+    if (buffers < 0 || buffers > 2) return fail(IGA_EINVAL, "buffers must be 0, 1 or 2");
+    plan->win_buffers[dir] = buffers;
+    if (plan->sched[dir].win && !plan->sched[dir].col) {
+        iga_status st = wsweep_prepare(plan, dir);
+        if (st) return st;
+    }
+    plan->graph.reset();
+    return IGA_OK;
+}
+
+int32_t iga_plan_window_buffers(const iga_plan *plan, int32_t dir)
+{
+    if (!plan || (dir != 0 && dir != 1)) return -1;
+    const Schedule &sc = plan->sched[dir];
+    if (!sc.win || sc.col) return 0;
+    return sc.compact ? 1 : 2;
+}
+
 iga_status iga_plan_set_column_schedule(iga_plan *plan, int32_t rows_per_chunk)
 {
     if (!plan) return fail(IGA_EINVAL, "plan is NULL");

@@ -81,6 +81,7 @@ struct Schedule {
     int lines = 4, wpl = 1, mm = 17;
     int win = 0;   // 1: windowed solves (see WinGeom), 0: exact chunk scan
     int col = 0;   // 1 (x-lines, FP32): column waves, mm rows per chunk (sweep_col.h)
+    int compact = 0;   // windowed: one line buffer per line (see WSweepParams)
 };
 
 // Windowed line solves (truncated partition): each lane restarts forward and
@@ -164,6 +165,7 @@ struct iga_plan {
     std::vector<double> op_band[iga::NOPS];    // host FP64 operators
     std::vector<double> cn_band[iga::NBANDS];  // explicit CN operators (B, or B - A)
     iga::Schedule sched[2];
+    int win_buffers[2] = {0, 0};   // requested windowed LDS form: 0 automatic, 1 or 2 buffers
     int asm_rows = 16;
     int asm_stack = 0;   // assembly tiles share halos within four-tile workgroups
 
@@ -255,9 +257,9 @@ iga_status build_assemble_batch(const std::vector<iga_plan *> &pls, const std::v
 iga_status launch_batch(const BatchLaunch &b, hipStream_t s);
 iga_status sweep_prepare(const iga_plan *pl, int dir);
 size_t sweep_lds_bytes(const iga_plan *pl, int dir, int lines, int wpl);
-size_t wsweep_lds_bytes(const iga_plan *pl, int dir, int lines, int wpl, int mm);
+size_t wsweep_lds_bytes(const iga_plan *pl, int dir, int lines, int wpl, int mm, int compact = 0);
 int wsweep_max_block(bool fp32, int mm);   // largest workgroup the windowed kernel allows
-iga_status wsweep_prepare(const iga_plan *pl, int dir);
+iga_status wsweep_prepare(iga_plan *pl, int dir);
 
 // kernels (util)
 iga_status launch_nonfinite(const iga_plan *pl, const void *T, const void *fuel, int *flag,

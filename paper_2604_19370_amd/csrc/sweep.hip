@@ -110,30 +110,30 @@ static iga_status build_params(const iga_plan *pl, int dir, const SweepJob *jobs
 // ---------------------------------------------------------------------------
 // windowed solves
 // ---------------------------------------------------------------------------
-static WSweepFn pick_wfn(bool fp32, int P, int mm, bool diry)
+static WSweepFn pick_wfn(bool fp32, int P, int mm, bool diry, bool one)
 {
     if (fp32) {
-        if (P == 1) return pick_wsweep_f1(mm, diry);
-        if (P == 2) return pick_wsweep_f2(mm, diry);
-        if (P == 3) return pick_wsweep_f3(mm, diry);
+        if (P == 1) return pick_wsweep_f1(mm, diry, one);
+        if (P == 2) return pick_wsweep_f2(mm, diry, one);
+        if (P == 3) return pick_wsweep_f3(mm, diry, one);
     } else {
-        if (P == 1) return pick_wsweep_d1(mm, diry);
-        if (P == 2) return pick_wsweep_d2(mm, diry);
-        if (P == 3) return pick_wsweep_d3(mm, diry);
+        if (P == 1) return pick_wsweep_d1(mm, diry, one);
+        if (P == 2) return pick_wsweep_d2(mm, diry, one);
+        if (P == 3) return pick_wsweep_d3(mm, diry, one);
     }
     return nullptr;
 }
 
-static WSweepBatchFn pick_wbatch_fn(bool fp32, int P, int mm, bool diry)
+static WSweepBatchFn pick_wbatch_fn(bool fp32, int P, int mm, bool diry, bool one)
 {
     if (fp32) {
-        if (P == 1) return pick_wsweep_batch_f1(mm, diry);
-        if (P == 2) return pick_wsweep_batch_f2(mm, diry);
-        if (P == 3) return pick_wsweep_batch_f3(mm, diry);
+        if (P == 1) return pick_wsweep_batch_f1(mm, diry, one);
+        if (P == 2) return pick_wsweep_batch_f2(mm, diry, one);
+        if (P == 3) return pick_wsweep_batch_f3(mm, diry, one);
     } else {
-        if (P == 1) return pick_wsweep_batch_d1(mm, diry);
-        if (P == 2) return pick_wsweep_batch_d2(mm, diry);
-        if (P == 3) return pick_wsweep_batch_d3(mm, diry);
+        if (P == 1) return pick_wsweep_batch_d1(mm, diry, one);
+        if (P == 2) return pick_wsweep_batch_d2(mm, diry, one);
+        if (P == 3) return pick_wsweep_batch_d3(mm, diry, one);
     }
     return nullptr;
 }
@@ -146,22 +146,24 @@ static int wline_stride(int H, int wpl, int mm) { return 2 * H + 64 * wpl * mm; 
 // its job stages (nops factored operators with their refinement rows,
 // nbands bands); the launch takes the largest over its jobs.
 static size_t wlds(const iga_plan *pl, const WinGeom &g, int lines, int wpl, int mm, int nops,
-                   int nbands)
+                   int nbands, int compact)
 {
     const size_t w = pl->wsize;
     const int RS = 2 * pl->P + 2;
-    size_t b = align16((size_t)2 * lines * wline_stride(g.H, wpl, mm) * w);
+    size_t b = align16((size_t)(compact ? 1 : 2) * lines * wline_stride(g.H, wpl, mm) * w);
     const size_t op = align16((size_t)g.nrows * RS * w) + (pl->fp32 ? align16((size_t)g.anrows * RS * 8) : 0);
+    if (compact) nops = std::min(nops, 1);
     return b + 16 + nops * op + nbands * align16((size_t)g.anrows * RS * w);
 }
 
 // The largest job of a direction: x sweeps solve one operator; y sweeps may
 // solve, apply the Crank-Nicolson band and solve again (Strang S1 with S2).
-size_t wsweep_lds_bytes(const iga_plan *pl, int dir, int lines, int wpl, int mm)
+size_t wsweep_lds_bytes(const iga_plan *pl, int dir, int lines, int wpl, int mm, int compact)
 {
     const WinGeom g = window_geometry(pl, dir, mm, wpl);
     if (g.H <= 0) return ~(size_t)0;
-    return dir == 0 ? wlds(pl, g, lines, wpl, mm, 1, 0) : wlds(pl, g, lines, wpl, mm, 2, 1);
+    return dir == 0 ? wlds(pl, g, lines, wpl, mm, 1, 0, compact)
+                    : wlds(pl, g, lines, wpl, mm, 2, 1, compact);
 }
 
 static size_t wsweep_lds_jobs(const iga_plan *pl, int dir, const SweepJob *jobs, int njobs)
@@ -170,17 +172,30 @@ static size_t wsweep_lds_jobs(const iga_plan *pl, int dir, const SweepJob *jobs,
     size_t b = 0;
     for (int j = 0; j < njobs; ++j)
         b = std::max(b, wlds(pl, pl->wgeom[dir], sc.lines, sc.wpl, sc.mm,
-                             (jobs[j].op0 >= 0) + (jobs[j].op1 >= 0), jobs[j].band >= 0));
+                             (jobs[j].op0 >= 0) + (jobs[j].op1 >= 0), jobs[j].band >= 0, sc.compact));
     return b;
 }
 
-iga_status wsweep_prepare(const iga_plan *pl, int dir)
+// Also picks the compact form (one line buffer, tables staged in turn) where
+// it lets more workgroups share a compute unit than the two-buffer form:
+// both compute the same values in the same order, and the compact form
+// costs a few barriers, so it only pays where LDS limits residency.
+iga_status wsweep_prepare(iga_plan *pl, int dir)
 {
-    const Schedule &sc = pl->sched[dir];
-    WSweepFn fn = pick_wfn(pl->fp32, pl->P, sc.mm, dir == 1);
-    if (!fn) return fail(IGA_EUNSUPPORTED, "windowed line-solve kernel not compiled for this schedule");
-    IGA_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(fn),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
+    Schedule &sc = pl->sched[dir];
+    const int block = sc.lines * sc.wpl * 64;
+    int resident[2] = {0, 0};
+    for (int one = 0; one < 2; ++one) {
+        WSweepFn fn = pick_wfn(pl->fp32, pl->P, sc.mm, dir == 1, one != 0);
+        if (!fn) return fail(IGA_EUNSUPPORTED, "windowed line-solve kernel not compiled for this schedule");
+        IGA_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(fn),
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
+        const size_t lds = wsweep_lds_bytes(pl, dir, sc.lines, sc.wpl, sc.mm, one);
+        if (lds <= 160 * 1024)
+            IGA_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&resident[one], fn, block, lds));
+    }
+    const int req = pl->win_buffers[dir];
+    sc.compact = req == 1 ? 1 : req == 2 ? 0 : (resident[1] > resident[0] ? 1 : 0);
     return IGA_OK;
 }
 
@@ -214,8 +229,10 @@ static iga_status build_wparams(const iga_plan *pl, int dir, const SweepJob *job
     prm.W = sc.lines;
     prm.WPL = sc.wpl;
     prm.njobs = njobs;
+    prm.compact = sc.compact;
     return IGA_OK;
 }
+
 
 iga_status launch_sweep(const iga_plan *pl, int dir, const SweepJob *jobs, int njobs, hipStream_t s)
 {
@@ -225,7 +242,7 @@ iga_status launch_sweep(const iga_plan *pl, int dir, const SweepJob *jobs, int n
         return launch_csweep(pl, jobs, njobs, s);
     }
     if (sc.win) {
-        WSweepFn fn = pick_wfn(pl->fp32, pl->P, sc.mm, dir == 1);
+        WSweepFn fn = pick_wfn(pl->fp32, pl->P, sc.mm, dir == 1, sc.compact != 0);
         if (!fn) return fail(IGA_EUNSUPPORTED, "windowed line-solve kernel not compiled for this schedule");
         WSweepParams prm;
         iga_status st = build_wparams(pl, dir, jobs, njobs, prm);
@@ -274,7 +291,7 @@ iga_status build_sweep_batch(const std::vector<iga_plan *> &pls, int dir,
             // one launch per workgroup shape: members whose lines need fewer
             // wavefronts join with proportionally more lines per workgroup
             if (done[m] || sc.mm != key.mm || sc.lines * sc.wpl != key.lines * key.wpl ||
-                sc.win != key.win)
+                sc.win != key.win || (key.win && sc.compact != key.compact))
                 continue;
             done[m] = 1;
             int nlines, njobs;
@@ -302,7 +319,8 @@ iga_status build_sweep_batch(const std::vector<iga_plan *> &pls, int dir,
         }
         if (lds > 160 * 1024) return fail(IGA_EUNSUPPORTED, "line-solve tables do not fit in LDS");
         const void *fn = key.win
-            ? reinterpret_cast<const void *>(pick_wbatch_fn(pls[m0]->fp32, pls[m0]->P, key.mm, dir == 1))
+            ? reinterpret_cast<const void *>(pick_wbatch_fn(pls[m0]->fp32, pls[m0]->P, key.mm, dir == 1,
+                                                                  key.compact != 0))
             : reinterpret_cast<const void *>(pick_batch_fn(pls[m0]->fp32, pls[m0]->P, key.mm, dir == 1));
         if (!fn) return fail(IGA_EUNSUPPORTED, "line-solve kernel not compiled for this schedule");
         IGA_HIP(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));

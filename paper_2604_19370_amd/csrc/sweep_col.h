@@ -136,6 +136,9 @@ __device__ __forceinline__ void col_fence_on(float (&v)[K])
 // so every access is in bounds and needs no per-lane address register; the
 // uniform range test scales the value (a select on a loaded value lets the
 // compiler branch around each load).
+// INSIDE: every row of the block is known to lie in [0, N) (chunks whose
+// rows are all canonical), so no clamp or scaling is needed.
+template <bool INSIDE = false>
 __device__ __forceinline__ void col_load_block(float (&v)[CB], __amdgpu_buffer_rsrc_t rs, int voff,
                                                int first, int N, int ld)
 {
@@ -145,10 +148,14 @@ __device__ __forceinline__ void col_load_block(float (&v)[CB], __amdgpu_buffer_r
 #pragma unroll
     for (int u = 0; u < CB; ++u) {
         const int r = first + u;
-        const int rc = min(max(r, 0), N - 1);
-        const float in = __int_as_float((r >= 0 && r < N) ? 0x3f800000 : 0);
-        // the builtin returns the raw 32 bits
-        v[u] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, voff, rc * ld * 4, 0)) * in;
+        if constexpr (INSIDE) {
+            v[u] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, voff, r * ld * 4, 0));
+        } else {
+            const int rc = min(max(r, 0), N - 1);
+            const float in = __int_as_float((r >= 0 && r < N) ? 0x3f800000 : 0);
+            // the builtin returns the raw 32 bits
+            v[u] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, voff, rc * ld * 4, 0)) * in;
+        }
     }
 }
 
@@ -173,7 +180,7 @@ __device__ __forceinline__ void col_solve(const CSweepParams &prm, const CSweepJ
     constexpr int NY = MM + 2 * (HC + P) + HH;   // rows kept from the first forward pass
     constexpr int NR = MM + 2 * HC;              // rows of the residual / correction
     constexpr int NF = HH + NY;                  // rows of the first forward pass
-    constexpr int NFB = (NF + CB - 1) / CB, NRB = (NR + CB - 1) / CB;
+    constexpr int NFB = (NF + CB - 1) / CB;
     const int N = prm.N, ld = prm.ld;
     const CSweepOp &o = job.op;
     const int voff = min(j, prm.nlines - 1) * 4;   // in bounds for every lane
@@ -203,14 +210,19 @@ __device__ __forceinline__ void col_solve(const CSweepParams &prm, const CSweepJ
 #pragma unroll
     for (int q = 0; q < P; ++q) s[q] = 0.0f;
     float y[NY];
+    // b on the residual rows r0 - HC .. r0 + MM + HC - 1 (first-pass rows
+    // HH + P .. HH + P + NR - 1), kept from the first pass and overwritten
+    // in place by the residual and then the correction
+    constexpr int IB = HH + P;
+    float rr[NR];
     bool nz = false;
     {
         float bb[3][CB];
-        col_load_block(bb[0], rs, voff, rf, N, ld);
-        if (NFB > 1) col_load_block(bb[1], rs, voff, rf + CB, N, ld);
+        col_load_block<CANON>(bb[0], rs, voff, rf, N, ld);
+        if (NFB > 1) col_load_block<CANON>(bb[1], rs, voff, rf + CB, N, ld);
 #pragma unroll
         for (int blk = 0; blk < NFB; ++blk) {
-            if (blk + 2 < NFB) col_load_block(bb[(blk + 2) % 3], rs, voff, rf + (blk + 2) * CB, N, ld);
+            if (blk + 2 < NFB) col_load_block<CANON>(bb[(blk + 2) % 3], rs, voff, rf + (blk + 2) * CB, N, ld);
             col_fence();
 #pragma unroll
             for (int u = 0; u < CB; ++u) {
@@ -218,6 +230,7 @@ __device__ __forceinline__ void col_solve(const CSweepParams &prm, const CSweepJ
                 if (i < NF) {
                     const ColCoef<P> c = coef(rf + i);
                     float v = bb[blk % 3][u];
+                    if (i >= IB && i < IB + NR) rr[i - IB] = v;
                     if constexpr (ZS) nz = nz || v != 0.0f;
 #pragma unroll
                     for (int q = P - 1; q >= 0; --q) v -= c.l[q] * s[q];
@@ -257,40 +270,22 @@ __device__ __forceinline__ void col_solve(const CSweepParams &prm, const CSweepJ
         y[k] = v;   // x0 for k < NY - HH
     }
     // 2. residual in double on rows r0 - HC .. r0 + MM + HC - 1 (x0 at row
-    //    r - P + q is y[m + q]), over a sliding window of 2P+1 doubles; each
-    //    conversion is pinned to the block that consumes it
+    //    r - P + q is y[m + q]), over a sliding window of 2P+1 doubles
     const int rr0 = r0 - HC;
-    float rr[NR];
     {
         double w[2 * P + 1];
 #pragma unroll
         for (int q = 0; q < 2 * P; ++q) w[q + 1] = (double)y[q];
-        float bb[3][CB];
-        col_load_block(bb[0], rs, voff, rr0, N, ld);
-        if (NRB > 1) col_load_block(bb[1], rs, voff, rr0 + CB, N, ld);
 #pragma unroll
-        for (int blk = 0; blk < NRB; ++blk) {
-            if (blk + 2 < NRB) col_load_block(bb[(blk + 2) % 3], rs, voff, rr0 + (blk + 2) * CB, N, ld);
-            col_fence();
+        for (int m = 0; m < NR; ++m) {
 #pragma unroll
-            for (int u = 0; u < CB; ++u) {
-                const int m = blk * CB + u;
-                if (m < NR) {
-                    float yn = y[m + 2 * P];
-                    asm volatile("" : "+v"(yn));
+            for (int q = 0; q < 2 * P; ++q) w[q] = w[q + 1];
+            w[2 * P] = (double)y[m + 2 * P];
+            const ColA<P> a = acoef(rr0 + m);
+            double acc = (double)rr[m];
 #pragma unroll
-                    for (int q = 0; q < 2 * P; ++q) w[q] = w[q + 1];
-                    w[2 * P] = (double)yn;
-                    const ColA<P> a = acoef(rr0 + m);
-                    double acc = (double)bb[blk % 3][u];
-#pragma unroll
-                    for (int q = 0; q < 2 * P + 1; ++q) acc -= a.a[q] * w[q];
-                    rr[m] = (float)acc;
-                }
-            }
-            float last[1] = {rr[min(blk * CB + CB - 1, NR - 1)]};
-            col_fence_on(last);
-            rr[min(blk * CB + CB - 1, NR - 1)] = last[0];
+            for (int q = 0; q < 2 * P + 1; ++q) acc -= a.a[q] * w[q];
+            rr[m] = (float)acc;
         }
     }
     // 3. correction: forward from r0 - HC, backward from r0 + MM + HC - 1
@@ -331,21 +326,18 @@ __device__ __forceinline__ void col_solve(const CSweepParams &prm, const CSweepJ
     }
 }
 
-// One wavefront: column group and chunk quad from the block index (XCD-aware
-// order), chunk 4*quad + wave, job blockIdx.y.
+// One wavefront (the whole workgroup): column group and chunk from the
+// block index in XCD-aware order, job blockIdx.y.
 template <int P, int MM>
 __device__ __forceinline__ void csweep_body(const CSweepParams &prm)
 {
     constexpr int HH = ColHalo<P>::HH, HC = ColHalo<P>::HC;
-    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
-    // blocks dispatched to one XCD take consecutive chunk quads of a column
-    // group, so the halo rows two quads share are in that XCD's L2
-    const int nq = (prm.nchunks + 3) >> 2;
+    // blocks dispatched to one XCD take consecutive chunks of a column group,
+    // so the halo rows neighbouring chunks share are in that XCD's L2
     const int L = xcd_remap(blockIdx.x, gridDim.x);
-    const int cg = L / nq;
-    const int chunk = (L - cg * nq) * 4 + wave;
-    if (chunk >= prm.nchunks) return;   // whole wavefront
+    const int cg = L / prm.nchunks;
+    const int chunk = L - cg * prm.nchunks;
     const CSweepJob &job = prm.jobs[blockIdx.y];
     const int j = cg * 64 + lane;
     const bool jok = j < prm.nlines;
@@ -375,7 +367,7 @@ template <int P, int MM> struct ColWaves {
 };
 
 template <int P, int MM>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(ColWaves<P, MM>::value)))
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(ColWaves<P, MM>::value)))
 void k_csweep(CSweepParams prm)
 {
     csweep_body<P, MM>(prm);

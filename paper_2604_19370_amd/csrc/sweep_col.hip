@@ -70,8 +70,10 @@ iga_status launch_csweep(const iga_plan *pl, const SweepJob *jobs, int njobs, hi
     prm.ncg = (pl->Ny + 63) / 64;
     prm.nchunks = (pl->Nx + sc.mm - 1) / sc.mm;
     prm.njobs = njobs;
-    const int nblk = prm.ncg * ((prm.nchunks + 3) / 4);
-    hipLaunchKernelGGL(fn, dim3(nblk, njobs), dim3(256), 0, s, prm);
+    // one wavefront per workgroup: the waves share nothing, and single-wave
+    // workgroups retire independently
+    const int nblk = prm.ncg * prm.nchunks;
+    hipLaunchKernelGGL(fn, dim3(nblk, njobs), dim3(64), 0, s, prm);
     IGA_HIP(hipGetLastError());
     return IGA_OK;
 }

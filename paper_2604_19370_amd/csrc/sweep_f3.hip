@@ -5,7 +5,9 @@ namespace iga {
 SweepFn pick_sweep_f3(int mm, bool diry) { return pick_mm<float, 3>(mm, diry); }
 SweepBatchFn pick_sweep_batch_f3(int mm, bool diry) { return pick_mm_batch<float, 3>(mm, diry); }
 
-WSweepFn pick_wsweep_f3(int mm, bool diry) { return pick_wmm<float, 3>(mm, diry); }
-WSweepBatchFn pick_wsweep_batch_f3(int mm, bool diry) { return pick_wmm_batch<float, 3>(mm, diry); }
+WSweepFn pick_wsweep_f3(int mm, bool diry, bool one) { return pick_wmm<float, 3>(mm, diry, one); }
+WSweepBatchFn pick_wsweep_batch_f3(int mm, bool diry, bool one) {
+    return pick_wmm_batch<float, 3>(mm, diry, one);
+}
 
 }  // namespace iga

@@ -48,6 +48,8 @@ struct WSweepParams {
     int W;        // lines per workgroup (power of two)
     int WPL;      // wavefronts per line
     int njobs;
+    int compact;  // one line buffer per line (not two), and a second operator's
+                  // tables staged over the first's once its solve is done
 };
 
 template <typename T, int P, int MM> struct WinLane {
@@ -143,11 +145,14 @@ __device__ __forceinline__ void publish(T *buf, const T (&x)[MM], int r0)
 // One factored solve, x <- A^{-1} x.  `in` holds x's values for every lane
 // of the line (published, followed by a barrier); `tmp` is not being read.
 // On return `tmp` holds y and is still being read by other lanes.
+// With a single buffer (one: in == tmp) a barrier first lets every lane
+// finish reading its warm-up rows before y overwrites them.
 template <typename T, int P, int MM>
 __device__ __forceinline__ void wsolve(T (&x)[MM], const T *in, T *tmp, const T *tab,
-                                       const WinLane<T, P, MM> &ln, int H, int Hr)
+                                       const WinLane<T, P, MM> &ln, int H, int Hr, bool one)
 {
     wfwd<T, P, MM>(x, in, tab, ln, H, Hr);
+    if (one) __syncthreads();
     publish<T, MM>(tmp, x, ln.r0);
     __syncthreads();
     wbwd<T, P, MM>(x, tmp, tab, ln, H, Hr);
@@ -156,20 +161,23 @@ __device__ __forceinline__ void wsolve(T (&x)[MM], const T *in, T *tmp, const T 
 // x <- A^{-1} x with one FP64-residual refinement for FP32 plans.  Entry:
 // `bin` holds x (published), `bout` not being read.  Exit: both buffers may
 // still be read by other lanes (the caller synchronises before reuse).
+// one (bin == bout, a single buffer): each publish waits for the readers of
+// what it overwrites.
 template <typename T, int P, int MM>
 __device__ __forceinline__ void wsolve_refined(T (&x)[MM], T *bin, T *bout, const T *tab,
                                                const double *a64, const WinLane<T, P, MM> &ln,
-                                               int H, int Hc)
+                                               int H, int Hc, bool one)
 {
     if constexpr (sizeof(T) == 8) {
-        wsolve<T, P, MM>(x, bin, bout, tab, ln, H, H);
+        wsolve<T, P, MM>(x, bin, bout, tab, ln, H, H, one);
     } else {
         constexpr int RS = RowStride<P>::RS;
         T b[MM];
 #pragma unroll
         for (int k = 0; k < MM; ++k) b[k] = x[k];
-        wsolve<T, P, MM>(x, bin, bout, tab, ln, H, H);   // bin read (warm-up), bout = y
+        wsolve<T, P, MM>(x, bin, bout, tab, ln, H, H, one);   // bin read (warm-up), bout = y
         // x0 -> bin: bin's last readers passed the barrier inside wsolve
+        if (one) __syncthreads();
         publish<T, MM>(bin, x, ln.r0);
         __syncthreads();
         // residual b - A64 x0 in double (neighbour rows from bin)
@@ -190,10 +198,11 @@ __device__ __forceinline__ void wsolve_refined(T (&x)[MM], T *bin, T *bout, cons
             b[k] = (T)r;
         }
         // r -> bout: bout's last readers (backward warm-up) passed the barrier above
+        if (one) __syncthreads();
         publish<T, MM>(bout, b, ln.r0);
         __syncthreads();
         // correction: bin (x0) was last read by the residual, before that barrier
-        wsolve<T, P, MM>(b, bout, bin, tab, ln, H, Hc);
+        wsolve<T, P, MM>(b, bout, bin, tab, ln, H, Hc, one);
 #pragma unroll
         for (int k = 0; k < MM; ++k) x[k] += b[k];
     }
@@ -201,7 +210,9 @@ __device__ __forceinline__ void wsolve_refined(T (&x)[MM], T *bin, T *bout, cons
 
 // One workgroup's work: W lines starting at line blk*W, job `jobi`.  NB:
 // values of a line a thread loads at once (MM: all of them, see below).
-template <typename T, int P, int MM, bool DIRY, int NB>
+// ONE: the compact form (WSweepParams::compact), chosen at compile time
+// (as a run-time flag it made the compiler spill the chunk registers)
+template <typename T, int P, int MM, bool DIRY, int NB, bool ONE>
 __device__ __forceinline__ void wsweep_body(const WSweepParams &prm, const int blk, const int jobi)
 {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -326,11 +337,13 @@ __device__ __forceinline__ void wsweep_body(const WSweepParams &prm, const int b
     T lv[NB];
     if (WHOLE) fetch_lines(static_cast<const T *>(job.src), lv, 0);
 
-    // LDS: two line buffers [W][Lb] (row r of line l at H + l*Lb + r), then
-    // the tables of this job
+    // LDS: two line buffers [W][Lb] (row r of line l at H + l*Lb + r), or
+    // one in the compact form, then the tables of this job
+    constexpr bool one = ONE;
+    const int nbuf = one ? 1 : 2;
     T *bufA = reinterpret_cast<T *>(smem);
-    T *bufB = bufA + (size_t)W * Lb;
-    size_t off = ((size_t)2 * W * Lb * sizeof(T) + 15) & ~(size_t)15;
+    T *bufB = one ? bufA : bufA + (size_t)W * Lb;
+    size_t off = ((size_t)nbuf * W * Lb * sizeof(T) + 15) & ~(size_t)15;
     auto take = [&](size_t bytes) {
         unsigned char *p = smem + off;
         off += (bytes + 15) & ~(size_t)15;
@@ -351,20 +364,24 @@ __device__ __forceinline__ void wsweep_body(const WSweepParams &prm, const int b
     const bool has0 = job.op0 >= 0, has1 = job.op1 >= 0, hasb = job.band >= 0;
     int *flag = reinterpret_cast<int *>(take(16));   // workgroup-wide "input not all zero"
     if (tid == 0) *flag = 0;
+    // compact: a second operator reuses the first one's table space, staged
+    // there once the first solve is done (both have the direction's window
+    // geometry, so the same size)
+    const size_t off_op0 = off;
     if (has0) stage_op(prm.ops[job.op0], tab0, a640);
-    if (has1) stage_op(prm.ops[job.op1], tab1, a641);
+    if (has1 && !(one && has0)) stage_op(prm.ops[job.op1], tab1, a641);
     if (hasb) {
         T *r = reinterpret_cast<T *>(take((size_t)g.anrows * RS * sizeof(T)));
         stage_table_dma<T>(r, prm.bands[job.band].rows, g.anrows * RS);
         btab = r;
     }
     // zero the pads of every line buffer: [0, H) and [H + N, Lb)
-    for (int i = tid; i < 2 * W * H; i += blockDim.x) {
+    for (int i = tid; i < nbuf * W * H; i += blockDim.x) {
         const int l = i / H, r = i - l * H;
         bufA[(size_t)l * Lb + r] = T(0);
     }
     const int tailn = Lb - H - N;
-    for (int i = tid; i < 2 * W * tailn; i += blockDim.x) {
+    for (int i = tid; i < nbuf * W * tailn; i += blockDim.x) {
         const int l = i / tailn, r = i - l * tailn;
         bufA[(size_t)l * Lb + H + N + r] = T(0);
     }
@@ -412,11 +429,13 @@ __device__ __forceinline__ void wsweep_body(const WSweepParams &prm, const int b
     if (WHOLE && job.base) fetch_lines(static_cast<const T *>(job.base), lv, 0);
     // A: input published; B: free
     if (has0) {
-        wsolve_refined<T, P, MM>(x, A, B, tab0, a640, ln, H, Hc);
+        wsolve_refined<T, P, MM>(x, A, B, tab0, a640, ln, H, Hc, one);
         __syncthreads();
     }
     if (job.base) {
         // increment form: the solve produced x - base; add the base state
+        // (one buffer without a solve: the lanes' reads of the input first)
+        if (one && !has0) __syncthreads();
         if (WHOLE)
             put_lines(lv, bufB, 0);
         else
@@ -428,6 +447,12 @@ __device__ __forceinline__ void wsweep_body(const WSweepParams &prm, const int b
     }
     if (hasb) {
         // explicit Crank-Nicolson operator along the line, then the second solve
+        if (one && has0 && has1) {
+            // the first operator's tables were last read before the barrier
+            // that ended its solve; the barrier below makes these visible
+            off = off_op0;
+            stage_op(prm.ops[job.op1], tab1, a641);
+        }
         publish<T, MM>(A, x, ln.r0);
         __syncthreads();
         T xd[MM + 2 * P];
@@ -447,11 +472,13 @@ __device__ __forceinline__ void wsweep_body(const WSweepParams &prm, const int b
             for (int j = 0; j < 2 * P + 1; ++j) v += bt[k * RS + j] * xd[k + j];
             y[k] = v;
         }
-        // y -> B (free since the last barrier), then solve with A as scratch
+        // y -> B (free since the last barrier; one buffer: once every lane
+        // has read its neighbours' rows of x), then solve with A as scratch
+        if (one) __syncthreads();
         publish<T, MM>(B, y, ln.r0);
         __syncthreads();
         if (has1) {
-            wsolve_refined<T, P, MM>(y, B, A, tab1, a641, ln, H, Hc);
+            wsolve_refined<T, P, MM>(y, B, A, tab1, a641, ln, H, Hc, one);
             __syncthreads();
         }
         if (job.add_after) {
@@ -486,14 +513,14 @@ template <typename T, int P, int MM, bool BATCH> constexpr int wsweep_nb()
     return bytes <= fits ? MM : 4;
 }
 
-template <typename T, int P, int MM, bool DIRY>
+template <typename T, int P, int MM, bool DIRY, bool ONE>
 __global__ __launch_bounds__((wsweep_max_threads<T, P, MM>())) void k_wsweep(WSweepParams prm)
 {
-    wsweep_body<T, P, MM, DIRY, wsweep_nb<T, P, MM, false>()>(prm, xcd_remap(blockIdx.x, gridDim.x),
-                                                              blockIdx.y);
+    wsweep_body<T, P, MM, DIRY, wsweep_nb<T, P, MM, false>(), ONE>(prm, xcd_remap(blockIdx.x, gridDim.x),
+                                                                   blockIdx.y);
 }
 
-template <typename T, int P, int MM, bool DIRY>
+template <typename T, int P, int MM, bool DIRY, bool ONE>
 __global__ __launch_bounds__((wsweep_max_threads<T, P, MM>())) void k_wsweep_batch(
     const WSweepParams *__restrict__ prms, const int2 *__restrict__ info)
 {
@@ -501,7 +528,7 @@ __global__ __launch_bounds__((wsweep_max_threads<T, P, MM>())) void k_wsweep_bat
     if (bi.x < 0) return;
     const WSweepParams &prm = prms[bi.x];
     if ((int)blockIdx.y >= prm.njobs) return;
-    wsweep_body<T, P, MM, DIRY, wsweep_nb<T, P, MM, true>()>(prm, bi.y, blockIdx.y);
+    wsweep_body<T, P, MM, DIRY, wsweep_nb<T, P, MM, true>(), ONE>(prm, bi.y, blockIdx.y);
 }
 
 using WSweepFn = void (*)(WSweepParams);
@@ -509,35 +536,41 @@ using WSweepBatchFn = void (*)(const WSweepParams *, const int2 *);
 
 #define IGA_WSWEEP_MMS(X) X(9) X(13) X(17) X(25) X(33)
 
-template <typename T, int P> static WSweepFn pick_wmm(int mm, bool diry)
+template <typename T, int P> static WSweepFn pick_wmm(int mm, bool diry, bool one)
 {
-#define IGA_CASE(MM_) \
-    if (mm == MM_) return diry ? k_wsweep<T, P, MM_, true> : k_wsweep<T, P, MM_, false>;
+#define IGA_CASE(MM_)                                                                          \
+    if (mm == MM_)                                                                             \
+        return diry ? (one ? k_wsweep<T, P, MM_, true, true> : k_wsweep<T, P, MM_, true, false>) \
+                    : (one ? k_wsweep<T, P, MM_, false, true> : k_wsweep<T, P, MM_, false, false>);
     IGA_WSWEEP_MMS(IGA_CASE)
 #undef IGA_CASE
     return nullptr;
 }
 
-template <typename T, int P> static WSweepBatchFn pick_wmm_batch(int mm, bool diry)
+template <typename T, int P> static WSweepBatchFn pick_wmm_batch(int mm, bool diry, bool one)
 {
-#define IGA_CASE(MM_) \
-    if (mm == MM_) return diry ? k_wsweep_batch<T, P, MM_, true> : k_wsweep_batch<T, P, MM_, false>;
+#define IGA_CASE(MM_)                                                                     \
+    if (mm == MM_)                                                                        \
+        return diry ? (one ? k_wsweep_batch<T, P, MM_, true, true>                        \
+                           : k_wsweep_batch<T, P, MM_, true, false>)                      \
+                    : (one ? k_wsweep_batch<T, P, MM_, false, true>                       \
+                           : k_wsweep_batch<T, P, MM_, false, false>);
     IGA_WSWEEP_MMS(IGA_CASE)
 #undef IGA_CASE
     return nullptr;
 }
 
-WSweepFn pick_wsweep_f1(int mm, bool diry);
-WSweepFn pick_wsweep_d1(int mm, bool diry);
-WSweepBatchFn pick_wsweep_batch_f1(int mm, bool diry);
-WSweepBatchFn pick_wsweep_batch_d1(int mm, bool diry);
-WSweepFn pick_wsweep_f2(int mm, bool diry);
-WSweepFn pick_wsweep_f3(int mm, bool diry);
-WSweepFn pick_wsweep_d2(int mm, bool diry);
-WSweepFn pick_wsweep_d3(int mm, bool diry);
-WSweepBatchFn pick_wsweep_batch_f2(int mm, bool diry);
-WSweepBatchFn pick_wsweep_batch_f3(int mm, bool diry);
-WSweepBatchFn pick_wsweep_batch_d2(int mm, bool diry);
-WSweepBatchFn pick_wsweep_batch_d3(int mm, bool diry);
+WSweepFn pick_wsweep_f1(int mm, bool diry, bool one);
+WSweepFn pick_wsweep_d1(int mm, bool diry, bool one);
+WSweepBatchFn pick_wsweep_batch_f1(int mm, bool diry, bool one);
+WSweepBatchFn pick_wsweep_batch_d1(int mm, bool diry, bool one);
+WSweepFn pick_wsweep_f2(int mm, bool diry, bool one);
+WSweepFn pick_wsweep_f3(int mm, bool diry, bool one);
+WSweepFn pick_wsweep_d2(int mm, bool diry, bool one);
+WSweepFn pick_wsweep_d3(int mm, bool diry, bool one);
+WSweepBatchFn pick_wsweep_batch_f2(int mm, bool diry, bool one);
+WSweepBatchFn pick_wsweep_batch_f3(int mm, bool diry, bool one);
+WSweepBatchFn pick_wsweep_batch_d2(int mm, bool diry, bool one);
+WSweepBatchFn pick_wsweep_batch_d3(int mm, bool diry, bool one);
 
 }  // namespace iga

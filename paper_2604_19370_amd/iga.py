@@ -33,7 +33,8 @@ EXPORTED = ("iga_default_coeffs", "iga_plan_create", "iga_plan_destroy", "iga_pl
             "iga_plan_quadrature_points", "iga_plan_set_column_schedule",
             "iga_plan_set_assembly_stacking", "iga_plan_assembly_stacking",
             "iga_ensemble_set_assembly_stacking", "iga_step_noalloc", "iga_sample_points",
-            "iga_count_ambiguous", "iga_last_error")
+            "iga_count_ambiguous", "iga_plan_set_window_buffers", "iga_plan_window_buffers",
+            "iga_last_error")
 
 _COEFF_NAMES = ("c_adv", "c_diff", "c_react", "c_nld", "c_ign", "t_ig", "fuel_thr", "t_act",
                 "c_forcing", "c_rad", "fuel_rate")
@@ -120,10 +121,14 @@ def lib() -> ctypes.CDLL:
         L.iga_plan_assembly_stacking.argtypes = [vp]
         L.iga_plan_assembly_stacking.restype = i32
         L.iga_ensemble_set_assembly_stacking.argtypes = [vp, i32]
+        L.iga_plan_set_window_buffers.argtypes = [vp, i32, i32]
+        L.iga_plan_window_buffers.argtypes = [vp, i32]
+        L.iga_plan_window_buffers.restype = i32
         L.iga_last_error.argtypes = []
         L.iga_last_error.restype = ctypes.c_char_p
         for name in EXPORTED[1:-1]:
-            if name not in ("iga_plan_assembly_rows", "iga_plan_assembly_stacking"):
+            if name not in ("iga_plan_assembly_rows", "iga_plan_assembly_stacking",
+                            "iga_plan_window_buffers"):
                 getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -337,6 +342,15 @@ class Plan:
     def set_window_schedule(self, dir, lines, rows_per_lane=0):
         _check(lib().iga_plan_set_window_schedule(self._h, int(dir), int(lines), int(rows_per_lane)),
                "iga_plan_set_window_schedule")
+
+    def set_window_buffers(self, dir, buffers):
+        """LDS form of the windowed solves of `dir`: 0 automatic, 1 or 2 line buffers."""
+        _check(lib().iga_plan_set_window_buffers(self._h, int(dir), int(buffers)),
+               "iga_plan_set_window_buffers")
+
+    def window_buffers(self, dir) -> int:
+        """Line buffers of the windowed solves of `dir` in use (0: not windowed)."""
+        return int(lib().iga_plan_window_buffers(self._h, int(dir)))
 
     def set_column_schedule(self, rows_per_chunk=0):
         _check(lib().iga_plan_set_column_schedule(self._h, int(rows_per_chunk)),

@@ -55,6 +55,8 @@ def test_null_arguments_are_rejected():
     assert L.iga_line_solve(None, 0, 0, None, None) == iga.EINVAL
     assert L.iga_assemble_rhs(None, 0, None, None, None, None, None) == iga.EINVAL
     assert L.iga_plan_destroy(None) == iga.OK
+    assert L.iga_plan_set_window_buffers(None, 0, 0) == iga.EINVAL
+    assert L.iga_plan_window_buffers(None, 0) == -1
     bad_wind = iga.make_desc(16, 16, 2, 16.0, 16.0, 1e-3, "pr")
     bad_wind.wind.kind = 5
     h = ctypes.c_void_p()

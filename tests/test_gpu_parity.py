@@ -160,6 +160,45 @@ def test_line_solve_every_window_schedule(dir, lines, mm, n, p):
             assert rel(host(x), oracle.line_solve(od, dir, which, X)) < tol
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("p,scheme", [(1, "pr"), (2, "strang"), (2, "explicit"), (2, "pr")])
+def test_window_buffer_forms_bitwise_equal(precision, p, scheme):
+    """The windowed solves' two LDS forms -- one line buffer (a barrier
+    before every overwrite; a second operator's tables staged over the
+    first's once its solve is done) and two buffers -- compute the same
+    values in the same order: eager and graph-replayed steps through either
+    form agree bit for bit along both directions (ragged line counts, two
+    lines per workgroup), and the one-buffer form keeps per-step parity with
+    the oracle."""
+    print(f"window buffer forms {precision} p{p} {scheme}", flush=True)
+    fp32 = precision == "fp32"
+    sc = inputs.small_case(70 + p, 300, 171, p, scheme, dt=2e-3)
+    pl, od = plan_and_oracle(sc, precision)
+    for d in (0, 1):
+        pl.set_window_schedule(d, 2, 13)
+    out = {}
+    for form in (2, 1):
+        for d in (0, 1):
+            pl.set_window_buffers(d, form)
+            assert pl.window_buffers(d) == form
+        t, f = dev(sc.T0, fp32), dev(sc.fuel0, fp32)
+        for _ in range(4):
+            pl.step(t, f)
+        pl.run(t, f, 4)
+        out[form] = (t, f)
+    assert torch.equal(out[1][0], out[2][0]) and torch.equal(out[1][1], out[2][1])
+    per_step_parity(pl, od, sc, 2, precision)
+    # automatic choice: one of the two forms; switching to exact solves leaves none
+    pl.set_window_buffers(1, 0)
+    assert pl.window_buffers(1) in (1, 2)
+    pl.set_schedule(1, 1, 1)
+    assert pl.window_buffers(1) == 0
+    with pytest.raises(iga.IgaError) as e:
+        pl.set_window_buffers(1, 3)
+    assert e.value.status == iga.EINVAL
+    pl.close()
+
+
 def test_stiff_operators_fall_back_to_exact_solves():
     """With a time step far above the diffusive scale the implicit operators
     lose their fast decay (interior root of the forward recurrence ~0.945 at
