@@ -293,11 +293,13 @@ def end_of_run(scs, nsteps, sample_members=()):
 def report(rows, what):
     worst = {k: max(r[k] for r in rows)
              for k in ("T", "fuel", "points", "away", "points_away", "flipped_frac")}
+    worst["flipped_per_row"] = max(r["flipped"] / r["nel"] for r in rows)
     dburn = max(abs(r["burned32"] - r["burned64"]) for r in rows)
     print(f"{what}: FP32 vs FP64 over {len(rows)} members, worst rel L2 T {worst['T']:.3e}, "
           f"fuel {worst['fuel']:.3e}, T at 256^2 points {worst['points']:.3e}; away from dofs "
           f"off by > {pu.FLIP_K} K: T {worst['away']:.3e}, points {worst['points_away']:.3e}; "
-          f"largest fraction of such dofs {worst['flipped_frac']:.2e}; largest burned-element "
+          f"largest fraction of such dofs {worst['flipped_frac']:.2e} "
+          f"({worst['flipped_per_row']:.2f} per element row); largest burned-element "
           f"difference {dburn}", flush=True)
     for r in rows:
         print(f"  member {r['member']:2d} {r['nel']}^2: T {r['T']:.2e} fuel {r['fuel']:.2e} "
@@ -320,13 +322,18 @@ def assert_end_of_run(worst, dburn, max_burn, steps):
       prorated to `steps` (the float error grows with the step count:
       2.4e-6 after 200 steps at 1024^2; measured here 4.4e-6 / 8.3e-6 (T /
       points) after 300 steps, 6.4e-6 / 1.1e-5 after 500);
-    - such dofs are fewer than 1e-3 of all (measured up to 3.7e-4);
+    - such dofs lie along the fire front, whose length in elements grows
+      with the mesh side, so their number is bounded per element row of the
+      mesh: fewer than 2 per row (measured up to 0.40: 82 dofs of a 256^2
+      member, 290 of a 1024^2 one, 813 of a cubic 2048^2 one; which points
+      flip depends on the rounding, so on the schedules the autotuner
+      picks);
     - the burned areas agree to max_burn elements (an element whose centre
       fuel lies within float rounding of 0.1 can count either way; measured
       0-2)."""
     bound = 1e-5 * steps / 200
     assert worst["away"] < bound and worst["points_away"] < bound
-    assert worst["flipped_frac"] < 1e-3
+    assert worst["flipped_per_row"] < 2.0
     assert dburn <= max_burn
 
 
@@ -355,7 +362,7 @@ def test_sixty_four_uneven_members_300_steps():
               f"{fl['rel']:.3e} (dofs off by > {pu.FLIP_K} K: {fl['flipped']}, away "
               f"{fl['out_rel']:.3e})", flush=True)
         assert e64 < 2e-12
-        assert fl["out_rel"] < 1.5e-5 and fl["flipped_frac"] < 1e-3
+        assert fl["out_rel"] < 1.5e-5 and fl["flipped"] < 2 * sc.nel_x
 
 
 @pytest.mark.parametrize("scheme", ["pr", "strang"])
