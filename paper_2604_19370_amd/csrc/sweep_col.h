@@ -108,55 +108,43 @@ __device__ __forceinline__ ColA<P> col_a(const CSweepOp &o, int idx)
     return k;
 }
 
-// Rows are streamed from global memory in blocks of CB rows with loads
-// issued two blocks ahead; a compiler barrier between blocks keeps every load
-// of the fully unrolled passes from being hoisted to the top (which would
-// need a register per row).
-constexpr int CB = 8;
-
+// Keeps the compiler from moving instructions across this point (the loads
+// of a chunk's window stay ahead of its arithmetic).
 __device__ __forceinline__ void col_fence()
 {
     __builtin_amdgcn_sched_barrier(0);
     asm volatile("" ::: "memory");
 }
 
-// The same, and the values in v must be computed before it: keeps a block's
-// arithmetic from sinking below the next block's loads.
-template <int K>
-__device__ __forceinline__ void col_fence_on(float (&v)[K])
+// Near the line ends every row has its own coefficients (scalar loads):
+// a fence every other row keeps them from being issued (and held in scalar
+// registers) many rows ahead.
+template <bool CANON>
+__device__ __forceinline__ void col_row_fence(int i)
 {
-#pragma unroll
-    for (int i = 0; i < K; ++i) asm volatile("" : "+v"(v[i]) :: "memory");
-    __builtin_amdgcn_sched_barrier(0);
+    if constexpr (!CANON)
+        if (i & 1) col_fence();
 }
 
-// b values of rows first .. first + CB - 1 of this lane's column (0 outside
-// [0, N)).  Buffer loads: the lane's column (clamped to a valid one) is the
-// per-lane byte offset, the row (clamped to [0, N)) a uniform scalar offset,
-// so every access is in bounds and needs no per-lane address register; the
-// uniform range test scales the value (a select on a loaded value lets the
-// compiler branch around each load).
-// INSIDE: every row of the block is known to lie in [0, N) (chunks whose
-// rows are all canonical), so no clamp or scaling is needed.
-template <bool INSIDE = false>
-__device__ __forceinline__ void col_load_block(float (&v)[CB], __amdgpu_buffer_rsrc_t rs, int voff,
-                                               int first, int N, int ld)
+// b value of row base + off of this lane's column, the row clamped to [0, N) (the
+// caller zeroes rows outside [0, N) once the loads have returned, so no
+// per-row flag is held while they are in flight).  Buffer loads: the lane's
+// column (clamped to a valid one) is the per-lane byte offset, the row a
+// uniform scalar offset, so every access is in bounds and needs no per-lane
+// address register.  INSIDE: the row is known to lie in [0, N) (chunks whose
+// rows are all canonical).
+template <bool INSIDE>
+__device__ __forceinline__ float col_load_row(__amdgpu_buffer_rsrc_t rs, int voff, int base, int off,
+                                              int N, int ld)
 {
-    // the block's row is pinned here, so the scalar offsets of every block
-    // are not all computed (and kept) up front
-    asm volatile("" : "+s"(first));
-#pragma unroll
-    for (int u = 0; u < CB; ++u) {
-        const int r = first + u;
-        if constexpr (INSIDE) {
-            v[u] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, voff, r * ld * 4, 0));
-        } else {
-            const int rc = min(max(r, 0), N - 1);
-            const float in = __int_as_float((r >= 0 && r < N) ? 0x3f800000 : 0);
-            // the builtin returns the raw 32 bits
-            v[u] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, voff, rc * ld * 4, 0)) * in;
-        }
-    }
+    // row base + off: the base is pinned here, so the scalar offsets of the
+    // window's rows are neither computed (and held) before the first load
+    // nor kept for later passes
+    asm volatile("" : "+s"(base));
+    const int r = base + off;
+    const int rc = INSIDE ? r : min(max(r, 0), N - 1);
+    // the builtin returns the raw 32 bits
+    return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, voff, rc * ld * 4, 0));
 }
 
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t col_rsrc(const float *p, int N, int ld)
@@ -168,9 +156,8 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t col_rsrc(const float *p, int N
 
 // The refined solve of one chunk for this lane's column.  CANON: every row
 // in reach uses the canonical coefficients (passed in kc, ka).
-// ZS (zero-skip jobs): the first forward pass also tests its input; a
-// wavefront whose whole input window is zero stores zeros and stops (the
-// solve of zero data is exactly zero).
+// ZS (zero-skip jobs): a wavefront whose whole input window is zero stores
+// zeros and stops (the solve of zero data is exactly zero).
 template <int P, int MM, bool CANON, bool ZS>
 __device__ __forceinline__ void col_solve(const CSweepParams &prm, const CSweepJob &job,
                                           __amdgpu_buffer_rsrc_t rs, int r0, int j, bool jok,
@@ -180,70 +167,57 @@ __device__ __forceinline__ void col_solve(const CSweepParams &prm, const CSweepJ
     constexpr int NY = MM + 2 * (HC + P) + HH;   // rows kept from the first forward pass
     constexpr int NR = MM + 2 * HC;              // rows of the residual / correction
     constexpr int NF = HH + NY;                  // rows of the first forward pass
-    constexpr int NFB = (NF + CB - 1) / CB;
     const int N = prm.N, ld = prm.ld;
     const CSweepOp &o = job.op;
     const int voff = min(j, prm.nlines - 1) * 4;   // in bounds for every lane
     // per-row coefficients near the line ends: the row is pinned where it is
     // used, so the scalar loads are not all issued (and held) up front
-    auto coef = [&](int r) -> ColCoef<P> {
+    // (row base + off; the base is pinned before the offset is added, so the
+    // row is computed where it is used rather than kept from an earlier pass)
+    auto coef = [&](int base, int off) -> ColCoef<P> {
         if constexpr (CANON) {
             return kc;
         } else {
-            asm volatile("" : "+s"(r));
-            return col_coef<P>(o, col_row(r, N, o));
+            asm volatile("" : "+s"(base));
+            return col_coef<P>(o, col_row(base + off, N, o));
         }
     };
-    auto acoef = [&](int r) -> ColA<P> {
+    auto acoef = [&](int base, int off) -> ColA<P> {
         if constexpr (CANON) {
             return ka;
         } else {
-            asm volatile("" : "+s"(r));
-            return col_a<P>(o, col_row(r, N, o));
+            asm volatile("" : "+s"(base));
+            return col_a<P>(o, col_row(base + off, N, o));
         }
     };
 
-    // 1. first solve: forward over HH warm-up rows, then NY kept rows
+    // 1. first solve.  Every row of the window is loaded before the first is
+    //    used (one memory latency per chunk; the whole window fits in the
+    //    registers at this occupancy); forward substitution then overwrites
+    //    the loaded rows in place: v[HH + k] = y[k], the value of row ry + k
     const int ry = r0 - HC - P;   // row of y[0]
     const int rf = ry - HH;       // first row of the forward pass
-    float s[P];
+    constexpr int IB = HH + P;    // residual rows r0 - HC .. r0 + MM + HC - 1 are v[IB ..]
+    float v[NF];
 #pragma unroll
-    for (int q = 0; q < P; ++q) s[q] = 0.0f;
-    float y[NY];
-    // b on the residual rows r0 - HC .. r0 + MM + HC - 1 (first-pass rows
-    // HH + P .. HH + P + NR - 1), kept from the first pass and overwritten
-    // in place by the residual and then the correction
-    constexpr int IB = HH + P;
-    float rr[NR];
-    bool nz = false;
-    {
-        float bb[3][CB];
-        col_load_block<CANON>(bb[0], rs, voff, rf, N, ld);
-        if (NFB > 1) col_load_block<CANON>(bb[1], rs, voff, rf + CB, N, ld);
+    for (int i = 0; i < NF; ++i) v[i] = col_load_row<CANON>(rs, voff, rf, i, N, ld);
+    col_fence();
+    if constexpr (!CANON) {
+        // rows outside [0, N): window rows below lo or from hi on
+        const int lo = -rf, hi = N - rf;
 #pragma unroll
-        for (int blk = 0; blk < NFB; ++blk) {
-            if (blk + 2 < NFB) col_load_block<CANON>(bb[(blk + 2) % 3], rs, voff, rf + (blk + 2) * CB, N, ld);
-            col_fence();
-#pragma unroll
-            for (int u = 0; u < CB; ++u) {
-                const int i = blk * CB + u;   // row rf + i
-                if (i < NF) {
-                    const ColCoef<P> c = coef(rf + i);
-                    float v = bb[blk % 3][u];
-                    if (i >= IB && i < IB + NR) rr[i - IB] = v;
-                    if constexpr (ZS) nz = nz || v != 0.0f;
-#pragma unroll
-                    for (int q = P - 1; q >= 0; --q) v -= c.l[q] * s[q];
-#pragma unroll
-                    for (int q = P - 1; q > 0; --q) s[q] = s[q - 1];
-                    s[0] = v;
-                    if (i >= HH) y[i - HH] = v;
-                }
-            }
-            col_fence_on(s);
-        }
+        for (int i = 0; i < NF; ++i)
+            if (i < lo || i >= hi) v[i] = 0.0f;
     }
+    // b on the residual rows, kept for the residual and then overwritten in
+    // place by it and by the correction
+    float rr[NR];
+#pragma unroll
+    for (int m = 0; m < NR; ++m) rr[m] = v[IB + m];
     if constexpr (ZS) {
+        bool nz = false;
+#pragma unroll
+        for (int i = 0; i < NF; ++i) nz = nz || v[i] != 0.0f;
         if (!__any(nz)) {
             if (jok) {
                 float *dst = job.dst + j;
@@ -254,20 +228,36 @@ __device__ __forceinline__ void col_solve(const CSweepParams &prm, const CSweepJ
             return;
         }
     }
+    float s[P];
+#pragma unroll
+    for (int q = 0; q < P; ++q) s[q] = 0.0f;
+#pragma unroll
+    for (int i = 0; i < NF; ++i) {
+        const ColCoef<P> c = coef(rf, i);
+        float x = v[i];
+#pragma unroll
+        for (int q = P - 1; q >= 0; --q) x -= c.l[q] * s[q];
+#pragma unroll
+        for (int q = P - 1; q > 0; --q) s[q] = s[q - 1];
+        s[0] = x;
+        v[i] = x;
+        col_row_fence<CANON>(i);
+    }
     // backward from the top: rows NY - HH .. NY - 1 are the warm-up
     float t[P];
 #pragma unroll
     for (int q = 0; q < P; ++q) t[q] = 0.0f;
 #pragma unroll
     for (int k = NY - 1; k >= 0; --k) {
-        const ColCoef<P> c = coef(ry + k);
-        float v = y[k] * c.ui;
+        const ColCoef<P> c = coef(ry, k);
+        float x = v[HH + k] * c.ui;
 #pragma unroll
-        for (int q = P - 1; q >= 0; --q) v -= c.u[q] * t[q];
+        for (int q = P - 1; q >= 0; --q) x -= c.u[q] * t[q];
 #pragma unroll
         for (int q = P - 1; q > 0; --q) t[q] = t[q - 1];
-        t[0] = v;
-        y[k] = v;   // x0 for k < NY - HH
+        t[0] = x;
+        v[HH + k] = x;   // x0 for k < NY - HH
+        col_row_fence<CANON>(k);
     }
     // 2. residual in double on rows r0 - HC .. r0 + MM + HC - 1 (x0 at row
     //    r - P + q is y[m + q]), over a sliding window of 2P+1 doubles
@@ -275,17 +265,18 @@ __device__ __forceinline__ void col_solve(const CSweepParams &prm, const CSweepJ
     {
         double w[2 * P + 1];
 #pragma unroll
-        for (int q = 0; q < 2 * P; ++q) w[q + 1] = (double)y[q];
+        for (int q = 0; q < 2 * P; ++q) w[q + 1] = (double)v[HH + q];
 #pragma unroll
         for (int m = 0; m < NR; ++m) {
 #pragma unroll
             for (int q = 0; q < 2 * P; ++q) w[q] = w[q + 1];
-            w[2 * P] = (double)y[m + 2 * P];
-            const ColA<P> a = acoef(rr0 + m);
+            w[2 * P] = (double)v[HH + m + 2 * P];
+            const ColA<P> a = acoef(rr0, m);
             double acc = (double)rr[m];
 #pragma unroll
             for (int q = 0; q < 2 * P + 1; ++q) acc -= a.a[q] * w[q];
             rr[m] = (float)acc;
+            col_row_fence<CANON>(m);
         }
     }
     // 3. correction: forward from r0 - HC, backward from r0 + MM + HC - 1
@@ -293,27 +284,29 @@ __device__ __forceinline__ void col_solve(const CSweepParams &prm, const CSweepJ
     for (int q = 0; q < P; ++q) s[q] = 0.0f;
 #pragma unroll
     for (int m = 0; m < NR; ++m) {
-        const ColCoef<P> c = coef(rr0 + m);
-        float v = rr[m];
+        const ColCoef<P> c = coef(rr0, m);
+        float x = rr[m];
 #pragma unroll
-        for (int q = P - 1; q >= 0; --q) v -= c.l[q] * s[q];
+        for (int q = P - 1; q >= 0; --q) x -= c.l[q] * s[q];
 #pragma unroll
         for (int q = P - 1; q > 0; --q) s[q] = s[q - 1];
-        s[0] = v;
-        rr[m] = v;
+        s[0] = x;
+        rr[m] = x;
+        col_row_fence<CANON>(m);
     }
 #pragma unroll
     for (int q = 0; q < P; ++q) t[q] = 0.0f;
 #pragma unroll
     for (int m = NR - 1; m >= HC; --m) {
-        const ColCoef<P> c = coef(rr0 + m);
-        float v = rr[m] * c.ui;
+        const ColCoef<P> c = coef(rr0, m);
+        float x = rr[m] * c.ui;
 #pragma unroll
-        for (int q = P - 1; q >= 0; --q) v -= c.u[q] * t[q];
+        for (int q = P - 1; q >= 0; --q) x -= c.u[q] * t[q];
 #pragma unroll
         for (int q = P - 1; q > 0; --q) t[q] = t[q - 1];
-        t[0] = v;
-        rr[m] = v;
+        t[0] = x;
+        rr[m] = x;
+        col_row_fence<CANON>(m);
     }
     // 4. x = x0 + d on the own rows
     if (jok) {
@@ -321,7 +314,7 @@ __device__ __forceinline__ void col_solve(const CSweepParams &prm, const CSweepJ
 #pragma unroll
         for (int k = 0; k < MM; ++k) {
             const int r = r0 + k;
-            if (r < N) dst[(size_t)r * ld] = y[HC + P + k] + rr[HC + k];
+            if (r < N) dst[(size_t)r * ld] = v[HH + HC + P + k] + rr[HC + k];
         }
     }
 }
