@@ -153,7 +153,7 @@ static size_t wlds(const iga_plan *pl, const WinGeom &g, int lines, int wpl, int
     size_t b = align16((size_t)(compact ? 1 : 2) * lines * wline_stride(g.H, wpl, mm) * w);
     const size_t op = align16((size_t)g.nrows * RS * w) + (pl->fp32 ? align16((size_t)g.anrows * RS * 8) : 0);
     if (compact) nops = std::min(nops, 1);
-    return b + 16 + nops * op + nbands * align16((size_t)g.anrows * RS * w);
+    return b + 16 + 64 + nops * op + nbands * align16((size_t)g.anrows * RS * w);
 }
 
 // The largest job of a direction: x sweeps solve one operator; y sweeps may

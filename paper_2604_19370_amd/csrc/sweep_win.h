@@ -363,6 +363,21 @@ __device__ __forceinline__ void wsweep_body(const WSweepParams &prm, const int b
     };
     const bool has0 = job.op0 >= 0, has1 = job.op1 >= 0, hasb = job.band >= 0;
     int *flag = reinterpret_cast<int *>(take(16));   // workgroup-wide "input not all zero"
+    int *wnz = reinterpret_cast<int *>(take(64));    // the same per wavefront
+    // A zero-skip job whose lines are all zero has nothing to do: the result
+    // (zero, or the base it is added to) is already in dst.  With the whole
+    // chunk in registers this is known before any table is staged.
+    if (WHOLE && job.zero_skip) {
+        bool nz = false;
+#pragma unroll
+        for (int k = 0; k < NB; ++k) nz = nz || lv[k] != T(0);
+        const bool wz = __any(nz);
+        if (lane == 0) wnz[wave] = wz ? 1 : 0;
+        __syncthreads();
+        int any = 0;
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) any |= wnz[w];
+        if (!any) return;   // the same value for every thread of the workgroup
+    }
     if (tid == 0) *flag = 0;
     // compact: a second operator reuses the first one's table space, staged
     // there once the first solve is done (both have the direction's window
@@ -416,7 +431,7 @@ __device__ __forceinline__ void wsweep_body(const WSweepParams &prm, const int b
     T x[MM];
 #pragma unroll
     for (int k = 0; k < MM; ++k) x[k] = live ? A[ln.r0 + k] : T(0);
-    if (job.zero_skip) {
+    if (!WHOLE && job.zero_skip) {
         // all-zero input lines: the result (zero, or the base it is added to)
         // is already in dst
         bool nz = false;
