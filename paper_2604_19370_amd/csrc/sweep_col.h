@@ -50,6 +50,8 @@ struct CSweepParams {
     int ld;        // row stride of the field (Ny)
     int ncg;       // column groups of 64 lines
     int nchunks;   // chunks of MM rows per line
+    int lo_end;    // chunks [0, lo_end) and [hi_start, nchunks) reach rows outside
+    int hi_start;  // the canonical interior of some job's operator
     int njobs;
 };
 
@@ -326,11 +328,24 @@ __device__ __forceinline__ void csweep_body(const CSweepParams &prm)
 {
     constexpr int HH = ColHalo<P>::HH, HC = ColHalo<P>::HC;
     const int lane = threadIdx.x & 63;
-    // blocks dispatched to one XCD take consecutive chunks of a column group,
-    // so the halo rows neighbouring chunks share are in that XCD's L2
-    const int L = xcd_remap(blockIdx.x, gridDim.x);
-    const int cg = L / prm.nchunks;
-    const int chunk = L - cg * prm.nchunks;
+    // Chunks near the line ends load their coefficients row by row and take
+    // longest: they get the first blocks, which the dispatcher spreads over
+    // the XCDs and starts first.  The interior chunks follow; blocks
+    // dispatched to one XCD take consecutive chunks of a column group, so
+    // the halo rows neighbouring chunks share are in that XCD's L2.
+    const int nlo = prm.lo_end, nedge = nlo + prm.nchunks - prm.hi_start;
+    const int nint = prm.hi_start - nlo;
+    const int b = blockIdx.x, e0 = prm.ncg * nedge;
+    int cg, chunk;
+    if (b < e0) {
+        cg = b / nedge;
+        const int e = b - cg * nedge;
+        chunk = e < nlo ? e : prm.hi_start + (e - nlo);
+    } else {
+        const int L = xcd_remap(b - e0, gridDim.x - e0);
+        cg = L / nint;
+        chunk = nlo + (L - cg * nint);
+    }
     const CSweepJob &job = prm.jobs[blockIdx.y];
     const int j = cg * 64 + lane;
     const bool jok = j < prm.nlines;

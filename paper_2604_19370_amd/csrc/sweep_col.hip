@@ -70,6 +70,24 @@ iga_status launch_csweep(const iga_plan *pl, const SweepJob *jobs, int njobs, hi
     prm.ncg = (pl->Ny + 63) / 64;
     prm.nchunks = (pl->Nx + sc.mm - 1) / sc.mm;
     prm.njobs = njobs;
+    // chunks whose rows (with their warm-ups) leave the canonical interior of
+    // some job's operator: the first lo_end and those from hi_start on
+    {
+        int hh = 0;
+        if (pl->P == 1) hh = ColHalo<1>::HH + ColHalo<1>::HC + 1;
+        if (pl->P == 2) hh = ColHalo<2>::HH + ColHalo<2>::HC + 2;
+        if (pl->P == 3) hh = ColHalo<3>::HH + ColHalo<3>::HC + 3;
+        int k0 = 0, nk = pl->Nx;
+        for (int i = 0; i < njobs; ++i) {
+            k0 = std::max(k0, prm.jobs[i].op.K0);
+            nk = std::min(nk, prm.jobs[i].op.NK);
+        }
+        const int lo = std::min(prm.nchunks, (k0 + hh + sc.mm - 1) / sc.mm);
+        const int top = nk - sc.mm - hh;   // last canonical chunk starts at or below this row
+        const int hi = top >= 0 ? top / sc.mm + 1 : 0;
+        prm.lo_end = lo;
+        prm.hi_start = std::min(prm.nchunks, std::max(lo, hi));
+    }
     // one wavefront per workgroup: the waves share nothing, and single-wave
     // workgroups retire independently
     const int nblk = prm.ncg * prm.nchunks;
