@@ -184,6 +184,10 @@ struct iga_plan {
     iga::DevBuf asm_wx, asm_wy;                // wind remainders at x-qps / y-qps
     iga::DevBuf scratch_r, scratch_rf;         // right-hand sides
     iga::DevBuf scratch_r2, scratch_rf2;       // x-solved right-hand sides (column waves)
+    // column waves: edge windows of the x operators for the current chunk
+    // size (ColEdge in sweep_col.h) and the edge chunks [0, col_lo), [col_hi, ..)
+    iga::DevBuf col_edge_f[iga::NOPS], col_edge_d[iga::NOPS];
+    int col_lo = 0, col_hi = 0;
     iga::DevBuf flag;                          // non-finite detector
     bool factored = false;
     iga::GraphCache graph;
@@ -232,6 +236,7 @@ iga_status launch_sweep(const iga_plan *pl, int dir, const SweepJob *jobs, int n
 bool csweep_ok(const iga_plan *pl);
 bool csweep_rows_ok(int mm);
 iga_status launch_csweep(const iga_plan *pl, const SweepJob *jobs, int njobs, hipStream_t s);
+iga_status build_column_edges(iga_plan *pl, int mm);   // edge windows for chunks of mm rows
 int sweep_capacity(int m);           // smallest compiled register capacity >= m (0: none)
 
 // A prepared batched launch over ensemble members: kernel, per-member

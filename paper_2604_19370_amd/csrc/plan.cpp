@@ -736,6 +736,8 @@ iga_status choose_column_schedule(iga_plan *pl, int mm)
                                       "within the kernel's warm-ups");
     if ((size_t)pl->Nx * pl->Ny * 4 >= ((size_t)1 << 31))
         return fail(IGA_EUNSUPPORTED, "column-wave solves address fields below 2 GiB");
+    iga_status st = build_column_edges(pl, mm);
+    if (st) return st;
     Schedule &sc = pl->sched[0];
     sc.lines = 1;
     sc.wpl = 1;

@@ -33,6 +33,8 @@ constexpr int CMAXJOBS = 2;
 struct CSweepOp {
     const float *rows;    // compressed factor rows [nrows][RS] (L, 1/U, U/U_rr)
     const double *a64;    // compressed operator rows [nrows][RS] (A(r, r-P .. r+P))
+    const float *ef;      // edge windows (ColEdge): factor coefficients in pass order
+    const double *ed;     // edge windows: operator rows of the residual
     int K0, NK, ID;       // rows [0, K0) and [NK, N) stored; interior -> row K0; ID identity row
 };
 
@@ -60,12 +62,25 @@ template <> struct ColHalo<1> { static constexpr int HH = 12, HC = 8; };
 template <> struct ColHalo<2> { static constexpr int HH = 20, HC = 12; };
 template <> struct ColHalo<3> { static constexpr int HH = 28, HC = 20; };
 
-// table row of line row r (identity outside [0, N)), without branches
-__device__ __forceinline__ int col_row(int r, int N, const CSweepOp &o)
-{
-    const int in = min(r, o.K0) + max(0, r - o.NK + 1);
-    return (r >= 0 && r < N) ? in : o.ID;
-}
+// Chunks whose windows reach rows outside an x operator's canonical interior
+// (the first lo_end and those from hi_start on, "edge chunks") read their
+// coefficients from edge windows the plan builds: for edge chunk e, the
+// coefficients of each window row in the order the passes use them, so a
+// pass reads them at compile-time offsets from one base (scalar loads of
+// consecutive words).  Floats: forward l of window rows 0 .. NF-1 (P each),
+// backward (1/U, u) of window rows HH .. HH+NY-1 (P+1 each), correction
+// forward l and backward (1/U, u) of window rows IB .. IB+NR-1; doubles: the
+// operator row A(r, r-P .. r+P) of the residual rows (2P+1 each).  Window
+// row w is line row r0 - HC - P - HH + w; rows outside the line take the
+// identity row.
+template <int P, int MM> struct ColEdge {
+    static constexpr int HH = ColHalo<P>::HH, HC = ColHalo<P>::HC;
+    static constexpr int NY = MM + 2 * (HC + P) + HH, NR = MM + 2 * HC, NF = HH + NY;
+    static constexpr int IB = HH + P;
+    static constexpr int FL = 0, BU = FL + NF * P, CL = BU + NY * (P + 1), CU = CL + NR * P;
+    static constexpr int NFLT = CU + NR * (P + 1);
+    static constexpr int NDBL = NR * (2 * P + 1);
+};
 
 // The tables are read-only during a launch: read them through the constant
 // address space, so uniform reads are scalar loads even after the kernel's
@@ -118,14 +133,14 @@ __device__ __forceinline__ void col_fence()
     asm volatile("" ::: "memory");
 }
 
-// Near the line ends every row has its own coefficients (scalar loads):
-// a fence every other row keeps them from being issued (and held in scalar
-// registers) many rows ahead.
+// Edge chunks read their coefficients with scalar loads: a fence every 8
+// rows keeps them from all being issued (and held in scalar registers) at
+// once.
 template <bool CANON>
 __device__ __forceinline__ void col_row_fence(int i)
 {
     if constexpr (!CANON)
-        if (i & 1) col_fence();
+        if ((i & 7) == 7) col_fence();
 }
 
 // b value of row base + off of this lane's column, the row clamped to [0, N) (the
@@ -163,7 +178,7 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t col_rsrc(const float *p, int N
 template <int P, int MM, bool CANON, bool ZS>
 __device__ __forceinline__ void col_solve(const CSweepParams &prm, const CSweepJob &job,
                                           __amdgpu_buffer_rsrc_t rs, int r0, int j, bool jok,
-                                          const ColCoef<P> &kc, const ColA<P> &ka)
+                                          const ColCoef<P> &kc, const ColA<P> &ka, int edge)
 {
     constexpr int HH = ColHalo<P>::HH, HC = ColHalo<P>::HC;
     constexpr int NY = MM + 2 * (HC + P) + HH;   // rows kept from the first forward pass
@@ -172,24 +187,40 @@ __device__ __forceinline__ void col_solve(const CSweepParams &prm, const CSweepJ
     const int N = prm.N, ld = prm.ld;
     const CSweepOp &o = job.op;
     const int voff = min(j, prm.nlines - 1) * 4;   // in bounds for every lane
-    // per-row coefficients near the line ends: the row is pinned where it is
-    // used, so the scalar loads are not all issued (and held) up front
-    // (row base + off; the base is pinned before the offset is added, so the
-    // row is computed where it is used rather than kept from an earlier pass)
-    auto coef = [&](int base, int off) -> ColCoef<P> {
+    // coefficients: the canonical set, or the chunk's edge window (ColEdge),
+    // one accessor per pass, each at a compile-time offset
+    using E = ColEdge<P, MM>;
+    const auto ef = col_const(o.ef) + (size_t)(CANON ? 0 : edge) * E::NFLT;
+    const auto ed = col_const(o.ed) + (size_t)(CANON ? 0 : edge) * E::NDBL;
+    auto lrow = [&](int off) -> ColCoef<P> {   // forward: l only
         if constexpr (CANON) {
             return kc;
         } else {
-            asm volatile("" : "+s"(base));
-            return col_coef<P>(o, col_row(base + off, N, o));
+            ColCoef<P> k = kc;
+#pragma unroll
+            for (int q = 0; q < P; ++q) k.l[q] = ef[off + q];
+            return k;
         }
     };
-    auto acoef = [&](int base, int off) -> ColA<P> {
+    auto urow = [&](int off) -> ColCoef<P> {   // backward: 1/U and u
+        if constexpr (CANON) {
+            return kc;
+        } else {
+            ColCoef<P> k = kc;
+            k.ui = ef[off];
+#pragma unroll
+            for (int q = 0; q < P; ++q) k.u[q] = ef[off + 1 + q];
+            return k;
+        }
+    };
+    auto acoef = [&](int m) -> ColA<P> {
         if constexpr (CANON) {
             return ka;
         } else {
-            asm volatile("" : "+s"(base));
-            return col_a<P>(o, col_row(base + off, N, o));
+            ColA<P> k;
+#pragma unroll
+            for (int q = 0; q < 2 * P + 1; ++q) k.a[q] = ed[m * (2 * P + 1) + q];
+            return k;
         }
     };
 
@@ -235,7 +266,7 @@ __device__ __forceinline__ void col_solve(const CSweepParams &prm, const CSweepJ
     for (int q = 0; q < P; ++q) s[q] = 0.0f;
 #pragma unroll
     for (int i = 0; i < NF; ++i) {
-        const ColCoef<P> c = coef(rf, i);
+        const ColCoef<P> c = lrow(E::FL + i * P);
         float x = v[i];
 #pragma unroll
         for (int q = P - 1; q >= 0; --q) x -= c.l[q] * s[q];
@@ -251,7 +282,7 @@ __device__ __forceinline__ void col_solve(const CSweepParams &prm, const CSweepJ
     for (int q = 0; q < P; ++q) t[q] = 0.0f;
 #pragma unroll
     for (int k = NY - 1; k >= 0; --k) {
-        const ColCoef<P> c = coef(ry, k);
+        const ColCoef<P> c = urow(E::BU + k * (P + 1));
         float x = v[HH + k] * c.ui;
 #pragma unroll
         for (int q = P - 1; q >= 0; --q) x -= c.u[q] * t[q];
@@ -273,7 +304,7 @@ __device__ __forceinline__ void col_solve(const CSweepParams &prm, const CSweepJ
 #pragma unroll
             for (int q = 0; q < 2 * P; ++q) w[q] = w[q + 1];
             w[2 * P] = (double)v[HH + m + 2 * P];
-            const ColA<P> a = acoef(rr0, m);
+            const ColA<P> a = acoef(m);
             double acc = (double)rr[m];
 #pragma unroll
             for (int q = 0; q < 2 * P + 1; ++q) acc -= a.a[q] * w[q];
@@ -286,7 +317,7 @@ __device__ __forceinline__ void col_solve(const CSweepParams &prm, const CSweepJ
     for (int q = 0; q < P; ++q) s[q] = 0.0f;
 #pragma unroll
     for (int m = 0; m < NR; ++m) {
-        const ColCoef<P> c = coef(rr0, m);
+        const ColCoef<P> c = lrow(E::CL + m * P);
         float x = rr[m];
 #pragma unroll
         for (int q = P - 1; q >= 0; --q) x -= c.l[q] * s[q];
@@ -300,7 +331,7 @@ __device__ __forceinline__ void col_solve(const CSweepParams &prm, const CSweepJ
     for (int q = 0; q < P; ++q) t[q] = 0.0f;
 #pragma unroll
     for (int m = NR - 1; m >= HC; --m) {
-        const ColCoef<P> c = coef(rr0, m);
+        const ColCoef<P> c = urow(E::CU + m * (P + 1));
         float x = rr[m] * c.ui;
 #pragma unroll
         for (int q = P - 1; q >= 0; --q) x -= c.u[q] * t[q];
@@ -326,11 +357,10 @@ __device__ __forceinline__ void col_solve(const CSweepParams &prm, const CSweepJ
 template <int P, int MM>
 __device__ __forceinline__ void csweep_body(const CSweepParams &prm)
 {
-    constexpr int HH = ColHalo<P>::HH, HC = ColHalo<P>::HC;
     const int lane = threadIdx.x & 63;
-    // Chunks near the line ends load their coefficients row by row and take
-    // longest: they get the first blocks, which the dispatcher spreads over
-    // the XCDs and starts first.  The interior chunks follow; blocks
+    // Edge chunks load every row's coefficients and take longest: they get
+    // the first blocks, which the dispatcher spreads over the XCDs and
+    // starts first.  The interior chunks follow; blocks
     // dispatched to one XCD take consecutive chunks of a column group, so
     // the halo rows neighbouring chunks share are in that XCD's L2.
     const int nlo = prm.lo_end, nedge = nlo + prm.nchunks - prm.hi_start;
@@ -351,20 +381,20 @@ __device__ __forceinline__ void csweep_body(const CSweepParams &prm)
     const bool jok = j < prm.nlines;
     const int r0 = chunk * MM;
     const int N = prm.N;
-    // rows the first forward pass reads
-    const int rlo = r0 - HC - P - HH, rhi = r0 + MM + HC + P + HH;   // [rlo, rhi)
     const CSweepOp &o = job.op;
     // the buffer resource is built here, before the paths diverge, so it
     // stays in scalar registers
     const __amdgpu_buffer_rsrc_t rs = col_rsrc(job.src, N, prm.ld);
-    const bool canon = rlo >= o.K0 && rhi <= o.NK;
-    if (canon) {
-        const ColCoef<P> kc = col_coef<P>(o, o.K0);
-        const ColA<P> ka = col_a<P>(o, o.K0);
-        if (job.zero_skip) col_solve<P, MM, true, true>(prm, job, rs, r0, j, jok, kc, ka);
-        else col_solve<P, MM, true, false>(prm, job, rs, r0, j, jok, kc, ka);
+    // interior chunks use the canonical rows throughout (their windows lie in
+    // every x operator's canonical interior); edge chunks their edge window
+    const ColCoef<P> kc = col_coef<P>(o, o.K0);
+    const ColA<P> ka = col_a<P>(o, o.K0);
+    if (chunk >= prm.lo_end && chunk < prm.hi_start) {
+        if (job.zero_skip) col_solve<P, MM, true, true>(prm, job, rs, r0, j, jok, kc, ka, 0);
+        else col_solve<P, MM, true, false>(prm, job, rs, r0, j, jok, kc, ka, 0);
     } else {
-        col_solve<P, MM, false, false>(prm, job, rs, r0, j, jok, ColCoef<P>{}, ColA<P>{});
+        const int edge = chunk < prm.lo_end ? chunk : prm.lo_end + (chunk - prm.hi_start);
+        col_solve<P, MM, false, false>(prm, job, rs, r0, j, jok, kc, ka, edge);
     }
 }
 

@@ -39,6 +39,76 @@ bool csweep_ok(const iga_plan *pl)
     return true;
 }
 
+// Edge windows (ColEdge) of every x operator for chunks of mm rows.  The
+// edge chunks are those whose windows leave the canonical interior of some
+// x operator, so one range serves any mix of jobs.  A line row r maps to
+// the stored row min(r, K0) + max(0, r - NK + 1) of the compressed tables
+// (the interior shares row K0), rows outside [0, N) to the identity row;
+// factor values are rounded to float as in the state-precision tables.
+template <int P, int MM> static iga_status column_edges(iga_plan *pl)
+{
+    using E = ColEdge<P, MM>;
+    constexpr int RS = 2 * P + 2, W = 2 * P + 1, HS = E::HH + E::HC + P;
+    const int N = pl->Nx, nchunks = (N + MM - 1) / MM;
+    int k0 = 0, nk = N;
+    for (int op = 0; op < NOPS; ++op)
+        if (op_dir(op) == 0) {
+            k0 = std::max(k0, pl->op_host[op].K0);
+            nk = std::min(nk, pl->op_host[op].NK);
+        }
+    const int lo = std::min(nchunks, (k0 + HS + MM - 1) / MM);
+    const int top = nk - MM - HS;   // the last interior chunk starts at or below this row
+    const int hi = std::min(nchunks, std::max(lo, top >= 0 ? top / MM + 1 : 0));
+    const int nedge = lo + nchunks - hi;
+    for (int op = 0; op < NOPS; ++op) {
+        if (op_dir(op) != 0) continue;
+        const OpHost &o = pl->op_host[op];
+        auto row = [&](int r) -> int {   // stored row of line row r
+            if (r < 0 || r >= N) return o.nrows - 1;
+            return std::min(r, o.K0) + std::max(0, r - o.NK + 1);
+        };
+        std::vector<float> f((size_t)std::max(1, nedge) * E::NFLT, 0.f);
+        std::vector<double> d((size_t)std::max(1, nedge) * E::NDBL, 0.0);
+        for (int e = 0; e < nedge; ++e) {
+            const int c = e < lo ? e : hi + (e - lo);
+            const int rf = c * MM - HS;   // window row 0
+            float *fe = &f[(size_t)e * E::NFLT];
+            double *de = &d[(size_t)e * E::NDBL];
+            auto fr = [&](int w) { return &o.rows[(size_t)row(rf + w) * RS]; };
+            for (int w = 0; w < E::NF; ++w)
+                for (int q = 0; q < P; ++q) fe[E::FL + w * P + q] = (float)fr(w)[q];
+            for (int k = 0; k < E::NY; ++k)
+                for (int q = 0; q <= P; ++q) fe[E::BU + k * (P + 1) + q] = (float)fr(E::HH + k)[P + q];
+            for (int m = 0; m < E::NR; ++m) {
+                for (int q = 0; q < P; ++q) fe[E::CL + m * P + q] = (float)fr(E::IB + m)[q];
+                for (int q = 0; q <= P; ++q) fe[E::CU + m * (P + 1) + q] = (float)fr(E::IB + m)[P + q];
+                const double *a = &o.a64[(size_t)row(rf + E::IB + m) * RS];
+                for (int q = 0; q < W; ++q) de[m * W + q] = a[q];
+            }
+        }
+        IGA_HIP(pl->col_edge_f[op].alloc(f.size() * sizeof(float)));
+        IGA_HIP(hipMemcpy(pl->col_edge_f[op].ptr, f.data(), f.size() * sizeof(float), hipMemcpyHostToDevice));
+        IGA_HIP(pl->col_edge_d[op].alloc(d.size() * sizeof(double)));
+        IGA_HIP(hipMemcpy(pl->col_edge_d[op].ptr, d.data(), d.size() * sizeof(double), hipMemcpyHostToDevice));
+    }
+    pl->col_lo = lo;
+    pl->col_hi = hi;
+    return IGA_OK;
+}
+
+iga_status build_column_edges(iga_plan *pl, int mm)
+{
+#define IGA_CEDGE(M)                                                \
+    if (mm == M) {                                                  \
+        if (pl->P == 1) return column_edges<1, M>(pl);              \
+        if (pl->P == 2) return column_edges<2, M>(pl);              \
+        if (pl->P == 3) return column_edges<3, M>(pl);              \
+    }
+    IGA_CSWEEP_MMS(IGA_CEDGE)
+#undef IGA_CEDGE
+    return fail(IGA_EUNSUPPORTED, "column-wave edge windows: no kernel for this schedule");
+}
+
 iga_status launch_csweep(const iga_plan *pl, const SweepJob *jobs, int njobs, hipStream_t s)
 {
     const Schedule &sc = pl->sched[0];
@@ -59,6 +129,8 @@ iga_status launch_csweep(const iga_plan *pl, const SweepJob *jobs, int njobs, hi
         prm.jobs[i].zero_skip = j.zero_skip;
         prm.jobs[i].op.rows = pl->op_rows[j.op0].as<float>();
         prm.jobs[i].op.a64 = pl->op_a64c[j.op0].as<double>();
+        prm.jobs[i].op.ef = pl->col_edge_f[j.op0].as<float>();
+        prm.jobs[i].op.ed = pl->col_edge_d[j.op0].as<double>();
         // compressed rows: [0, K0), the canonical row K0, [NK, N), identity
         prm.jobs[i].op.K0 = o.K0;
         prm.jobs[i].op.NK = o.NK;
@@ -70,24 +142,8 @@ iga_status launch_csweep(const iga_plan *pl, const SweepJob *jobs, int njobs, hi
     prm.ncg = (pl->Ny + 63) / 64;
     prm.nchunks = (pl->Nx + sc.mm - 1) / sc.mm;
     prm.njobs = njobs;
-    // chunks whose rows (with their warm-ups) leave the canonical interior of
-    // some job's operator: the first lo_end and those from hi_start on
-    {
-        int hh = 0;
-        if (pl->P == 1) hh = ColHalo<1>::HH + ColHalo<1>::HC + 1;
-        if (pl->P == 2) hh = ColHalo<2>::HH + ColHalo<2>::HC + 2;
-        if (pl->P == 3) hh = ColHalo<3>::HH + ColHalo<3>::HC + 3;
-        int k0 = 0, nk = pl->Nx;
-        for (int i = 0; i < njobs; ++i) {
-            k0 = std::max(k0, prm.jobs[i].op.K0);
-            nk = std::min(nk, prm.jobs[i].op.NK);
-        }
-        const int lo = std::min(prm.nchunks, (k0 + hh + sc.mm - 1) / sc.mm);
-        const int top = nk - sc.mm - hh;   // last canonical chunk starts at or below this row
-        const int hi = top >= 0 ? top / sc.mm + 1 : 0;
-        prm.lo_end = lo;
-        prm.hi_start = std::min(prm.nchunks, std::max(lo, hi));
-    }
+    prm.lo_end = pl->col_lo;
+    prm.hi_start = pl->col_hi;
     // one wavefront per workgroup: the waves share nothing, and single-wave
     // workgroups retire independently
     const int nblk = prm.ncg * prm.nchunks;
