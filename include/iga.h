@@ -317,9 +317,11 @@ int32_t iga_plan_assembly_stacking(const iga_plan *plan);
  * plan's scratch buffers (T and fuel are only read), and keeps the fastest
  * of each (column waves included for the x-lines of FP32 plans).  The eight
  * fastest assembly tilings, then the eight fastest line-solve schedules of
- * each direction, are timed again as a captured graph of reps steps (as
- * iga_run replays them), on device copies of T and fuel that the call
- * allocates and frees, and the fastest step wins.  Synchronises `stream`; must follow iga_factor_1d.  reps >= 1
+ * each direction, then the tilings once more beside the chosen line solves,
+ * are timed again as a captured graph of reps steps (as
+ * iga_run replays them; the fastest of three replays counts), on device
+ * copies of T and fuel that the call allocates and frees, and the fastest
+ * step wins.  Synchronises `stream`; must follow iga_factor_1d.  reps >= 1
  * launches (or steps) per candidate. */
 iga_status iga_autotune(iga_plan *plan, const void *T, const void *fuel, int32_t reps,
                         void *stream);
