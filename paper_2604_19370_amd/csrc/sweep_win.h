@@ -3,7 +3,8 @@
 // Section 4's directional solves are independent banded LU solves per line.
 // Here a workgroup owns W lines, each worked by WPL wavefronts; lane c of a
 // line holds rows [c*MM, c*MM + MM) in registers, and the line is kept in LDS
-// in two buffers with H zero rows before and after it.  Forward substitution
+// in two buffers (one in the compact form, WSweepParams) with H zero rows
+// before and after it.  Forward substitution
 // is a linear recurrence whose state contracts geometrically for these
 // mass-dominated operators (the L and U factors of a banded Toeplitz-like
 // matrix); restarting it from a zero state H rows before the chunk reproduces
