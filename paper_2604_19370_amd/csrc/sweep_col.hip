@@ -60,6 +60,9 @@ template <int P, int MM> static iga_status column_edges(iga_plan *pl)
     const int top = nk - MM - HS;   // the last interior chunk starts at or below this row
     const int hi = std::min(nchunks, std::max(lo, top >= 0 ? top / MM + 1 : 0));
     const int nedge = lo + nchunks - hi;
+    // built aside and moved into the plan only when every table is on the
+    // device, so a failure leaves the current schedule's tables intact
+    DevBuf ef[NOPS], ed[NOPS];
     for (int op = 0; op < NOPS; ++op) {
         if (op_dir(op) != 0) continue;
         const OpHost &o = pl->op_host[op];
@@ -86,10 +89,15 @@ template <int P, int MM> static iga_status column_edges(iga_plan *pl)
                 for (int q = 0; q < W; ++q) de[m * W + q] = a[q];
             }
         }
-        IGA_HIP(pl->col_edge_f[op].alloc(f.size() * sizeof(float)));
-        IGA_HIP(hipMemcpy(pl->col_edge_f[op].ptr, f.data(), f.size() * sizeof(float), hipMemcpyHostToDevice));
-        IGA_HIP(pl->col_edge_d[op].alloc(d.size() * sizeof(double)));
-        IGA_HIP(hipMemcpy(pl->col_edge_d[op].ptr, d.data(), d.size() * sizeof(double), hipMemcpyHostToDevice));
+        IGA_HIP(ef[op].alloc(f.size() * sizeof(float)));
+        IGA_HIP(hipMemcpy(ef[op].ptr, f.data(), f.size() * sizeof(float), hipMemcpyHostToDevice));
+        IGA_HIP(ed[op].alloc(d.size() * sizeof(double)));
+        IGA_HIP(hipMemcpy(ed[op].ptr, d.data(), d.size() * sizeof(double), hipMemcpyHostToDevice));
+    }
+    for (int op = 0; op < NOPS; ++op) {
+        if (op_dir(op) != 0) continue;
+        pl->col_edge_f[op] = std::move(ef[op]);
+        pl->col_edge_d[op] = std::move(ed[op]);
     }
     pl->col_lo = lo;
     pl->col_hi = hi;
