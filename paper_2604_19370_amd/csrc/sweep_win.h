@@ -181,21 +181,26 @@ __device__ __forceinline__ void wsolve_refined(T (&x)[MM], T *bin, T *bout, cons
         if (one) __syncthreads();
         publish<T, MM>(bin, x, ln.r0);
         __syncthreads();
-        // residual b - A64 x0 in double (neighbour rows from bin)
+        // residual b - A64 x0 in double (neighbour rows from bin), over a
+        // sliding window of the 2P+1 rows r0 + k - P .. r0 + k + P, each
+        // converted when it enters (not all MM + 2P at once: registers)
         const double *a = a64 + (size_t)ln.ab * RS;
-        double xd[MM + 2 * P];
+        double w[2 * P + 1];
 #pragma unroll
         for (int i = 0; i < P; ++i) {
-            xd[i] = (double)bin[ln.r0 - P + i];
-            xd[MM + P + i] = (double)bin[ln.r0 + MM + i];
+            w[i + 1] = (double)bin[ln.r0 - P + i];
+            w[P + 1 + i] = (double)x[i];
         }
 #pragma unroll
-        for (int k = 0; k < MM; ++k) xd[P + k] = (double)x[k];
-#pragma unroll
         for (int k = 0; k < MM; ++k) {
+#pragma unroll
+            for (int q = 0; q < 2 * P; ++q) w[q] = w[q + 1];
+            T xn = k + P < MM ? x[k + P] : bin[ln.r0 + k + P];
+            asm volatile("" : "+v"(xn));   // converted here, not hoisted
+            w[2 * P] = (double)xn;
             double r = (double)b[k];
 #pragma unroll
-            for (int j = 0; j < 2 * P + 1; ++j) r -= a[k * RS + j] * xd[k + j];
+            for (int j = 0; j < 2 * P + 1; ++j) r -= a[k * RS + j] * w[j];
             b[k] = (T)r;
         }
         // r -> bout: bout's last readers (backward warm-up) passed the barrier above
@@ -239,8 +244,9 @@ __device__ __forceinline__ void wsweep_body(const WSweepParams &prm, const int b
     // line (64*WPL*MM >= N), NB at a time, each batch's loads issued before
     // its stores: a staging costs MM/NB memory latencies.  Where the whole
     // chunk fits in flight (NB == MM), the input lines load while the tables
-    // are staged and the increment form's base state loads while the line is
-    // solved.  y-lines: the WPL wavefronts of a line copy its contiguous run
+    // are staged, and the increment form's base state loads in one latency
+    // after the solve (held through it, its registers cost occupancy more
+    // than the latency costs).  y-lines: the WPL wavefronts of a line copy its contiguous run
     // of N values, 64 consecutive values per wavefront and instruction.
     // x-lines: rows of W consecutive columns; a workgroup slot past the last
     // line copies a live column into its own (unused) buffer.  Results use
@@ -442,7 +448,6 @@ __device__ __forceinline__ void wsweep_body(const WSweepParams &prm, const int b
         __syncthreads();
         if (!*flag) return;   // the same value for every thread of the workgroup
     }
-    if (WHOLE && job.base) fetch_lines(static_cast<const T *>(job.base), lv, 0);
     // A: input published; B: free
     if (has0) {
         wsolve_refined<T, P, MM>(x, A, B, tab0, a640, ln, H, Hc, one);
@@ -452,10 +457,12 @@ __device__ __forceinline__ void wsweep_body(const WSweepParams &prm, const int b
         // increment form: the solve produced x - base; add the base state
         // (one buffer without a solve: the lanes' reads of the input first)
         if (one && !has0) __syncthreads();
-        if (WHOLE)
+        if (WHOLE) {
+            fetch_lines(static_cast<const T *>(job.base), lv, 0);
             put_lines(lv, bufB, 0);
-        else
+        } else {
             load_lines(static_cast<const T *>(job.base), bufB);
+        }
         __syncthreads();
 #pragma unroll
         for (int k = 0; k < MM; ++k) x[k] += live ? B[ln.r0 + k] : T(0);
