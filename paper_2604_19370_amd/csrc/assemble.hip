@@ -190,10 +190,15 @@ __device__ __forceinline__ void assemble_body(const AsmParams<T> &a, const int s
     bool ram[Q];
     T acc0[Q][Q], acc1[Q][Q], accf[Q][Q];
     T pc0[Q], pc1[Q], pf0[Q], pf1[Q];
+    // live[s]: the dof row in slot s has received the contribution of an
+    // evaluated element (wavefront-uniform); a row without one is exactly zero
+    bool live[Q];
 #pragma unroll
-    for (int i = 0; i < Q; ++i)
+    for (int i = 0; i < Q; ++i) {
+        live[i] = false;
 #pragma unroll
         for (int q = 0; q < Q; ++q) acc0[i][q] = acc1[i][q] = accf[i][q] = T(0);
+    }
     // window rows E0 .. E0+P-1 in slots 0 .. P-1
 #pragma unroll
     for (int s = 0; s < P; ++s) {
@@ -305,41 +310,49 @@ __device__ __forceinline__ void assemble_body(const AsmParams<T> &a, const int s
                     }
                 }
             }
+#pragma unroll
+            for (int s = 0; s < Q; ++s) live[s] = true;
         } else {
 #pragma unroll
             for (int q = 0; q < Q; ++q) acc0[snew][q] = acc1[snew][q] = T(0);
+            live[snew] = false;
         }
         if (ex >= X0) {
             // dof row ex (slot ph) is complete: y weights, y half of the test
-            // contraction, gather from the p lanes to the left
+            // contraction, gather from the p lanes to the left.  A row that no
+            // evaluated element reached stores zero (what the contraction of
+            // its zero accumulators gives, +0, without evaluating it).
             constexpr int sd = ph;
-            T pb[Q], pf[Q];
-#pragma unroll
-            for (int q = 0; q < Q; ++q) {
-                acc0[sd][q] *= a.wyq[q];
-                acc1[sd][q] *= a.wyq[q];
-                if (FUEL) accf[sd][q] *= a.wyq[q];
-            }
-#pragma unroll
-            for (int b = 0; b < Q; ++b) {
-                T s0 = 0, s1 = 0;
+            T r = T(0), rf = T(0);
+            if (live[sd]) {
+                T pb[Q], pf[Q];
 #pragma unroll
                 for (int q = 0; q < Q; ++q) {
-                    s0 += acc0[sd][q] * byv[b][q] + acc1[sd][q] * byd[b][q];
-                    if (FUEL) s1 += accf[sd][q] * byv[b][q];
+                    acc0[sd][q] *= a.wyq[q];
+                    acc1[sd][q] *= a.wyq[q];
+                    if (FUEL) accf[sd][q] *= a.wyq[q];
                 }
-                pb[b] = s0;
-                pf[b] = s1;
-            }
-            T r = pb[0] + lane_behind<1>(pb[1]);
-            T rf = FUEL ? pf[0] + lane_behind<1>(pf[1]) : T(0);
-            if constexpr (Q > 2) {
-                r += lane_behind<2>(pb[2]);
-                if (FUEL) rf += lane_behind<2>(pf[2]);
-            }
-            if constexpr (Q > 3) {
-                r += lane_behind<3>(pb[3]);
-                if (FUEL) rf += lane_behind<3>(pf[3]);
+#pragma unroll
+                for (int b = 0; b < Q; ++b) {
+                    T s0 = 0, s1 = 0;
+#pragma unroll
+                    for (int q = 0; q < Q; ++q) {
+                        s0 += acc0[sd][q] * byv[b][q] + acc1[sd][q] * byd[b][q];
+                        if (FUEL) s1 += accf[sd][q] * byv[b][q];
+                    }
+                    pb[b] = s0;
+                    pf[b] = s1;
+                }
+                r = pb[0] + lane_behind<1>(pb[1]);
+                if (FUEL) rf = pf[0] + lane_behind<1>(pf[1]);
+                if constexpr (Q > 2) {
+                    r += lane_behind<2>(pb[2]);
+                    if (FUEL) rf += lane_behind<2>(pf[2]);
+                }
+                if constexpr (Q > 3) {
+                    r += lane_behind<3>(pb[3]);
+                    if (FUEL) rf += lane_behind<3>(pf[3]);
+                }
             }
             const int hi = ex - X0, ti = ex - X1;
             if (hold && hi < P) {
