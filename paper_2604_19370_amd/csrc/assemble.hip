@@ -161,12 +161,14 @@ __device__ __forceinline__ void assemble_body(const AsmParams<T> &a, const int s
             cb[3] = lane_ahead<3>(c0, c1, lane);
             fb[3] = lane_ahead<3>(f0, f1, lane);
         }
+        // (compare and select, not fmax: the inputs need no canonicalising,
+        // and a NaN coefficient leaves a NaN right-hand side either way)
         mx = cb[0];
         am = cb[0] == a.t_fix;
 #pragma unroll
         for (int b = 1; b < Q; ++b) {
-            mx = fmax(mx, cb[b]);
-            am = am && cb[b] == a.t_fix;
+            mx = cb[b] > mx ? cb[b] : mx;
+            am = am & (cb[b] == a.t_fix);
         }
 #pragma unroll
         for (int q = 0; q < Q; ++q) {
@@ -223,7 +225,7 @@ __device__ __forceinline__ void assemble_body(const AsmParams<T> &a, const int s
         // it contributes exactly nothing (the skip is wavefront-uniform)
         bool eam = ram[0];
 #pragma unroll
-        for (int s = 1; s < Q; ++s) eam = eam && ram[s];
+        for (int s = 1; s < Q; ++s) eam = eam & ram[s];
         const bool quiet = !SRC && a.amb && __all(!eyok || eam);
         if (ex >= 0 && ex < a.nel_x && ex < X1 && !quiet) {
             const int e2 = (ex >= P && ex < a.nel_x - P) ? P : ex;   // interior tables coincide
@@ -241,7 +243,7 @@ __device__ __forceinline__ void assemble_body(const AsmParams<T> &a, const int s
                 kyw[q] = (-a.cy - a.bca * a.wx[(size_t)ex * Q + q]) * a.wxq[q];
             T emx = rmx[0];
 #pragma unroll
-            for (int s = 1; s < Q; ++s) emx = fmax(emx, rmx[s]);
+            for (int s = 1; s < Q; ++s) emx = rmx[s] > emx ? rmx[s] : emx;
             const bool hot = FUEL ? (a.fuel_all || __any(emx > t_skip)) : __any(emx > t_skip);
             // linear, loss, forcing, wind and T^3-diffusion terms; the first
             // contribution to the fresh dof row (slot snew) is assigned
