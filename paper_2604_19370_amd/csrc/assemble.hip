@@ -127,27 +127,34 @@ __device__ __forceinline__ void assemble_body(const AsmParams<T> &a, const int s
         for (int qx = 0; qx < Q; ++qx) kxw[qx][qy] = k * a.wxq[qx];
     }
 
-    // raw coefficients of row `row` for columns colA (and colB for the halo)
-    // (rows past the tile's last element are never used: not loaded)
+    // raw coefficients of row `row` for columns colA (and colB for the halo).
+    // Every lane loads, from its column clamped into the mesh (lanes without
+    // a halo column repeat their own); columns outside the mesh are zeroed
+    // where the values are consumed, so no lane mask surrounds the loads.
+    // Rows from min(X1, nel_x) + p on only feed elements that are not
+    // evaluated: they are not loaded, and the registers keep what they held.
     const int rlim = min(X1, a.nel_x) + P;
+    const unsigned offA = (unsigned)min(max(colA, 0), Ny - 1) * (unsigned)sizeof(T);
+    const unsigned offB = okB ? (unsigned)colB * (unsigned)sizeof(T) : offA;
     auto fetch = [&](int row, T &c0, T &c1, T &f0, T &f1) {
-        c0 = c1 = f0 = f1 = T(0);
-        if (row >= 0 && row < rlim) {
-            const size_t base = (size_t)row * Ny;
-            if (okA) {
-                c0 = a.S[base + colA];
-                f0 = a.F[base + colA];
-            }
-            if (okB) {
-                c1 = a.S[base + colB];
-                f1 = a.F[base + colB];
-            }
+        if (row < rlim) {
+            const size_t rb = (size_t)max(row, 0) * Ny * sizeof(T);
+            const char *sr = reinterpret_cast<const char *>(a.S) + rb;
+            const char *fr = reinterpret_cast<const char *>(a.F) + rb;
+            c0 = *reinterpret_cast<const T *>(sr + offA);
+            f0 = *reinterpret_cast<const T *>(fr + offA);
+            c1 = *reinterpret_cast<const T *>(sr + offB);
+            f1 = *reinterpret_cast<const T *>(fr + offB);
         }
     };
     // y half of the sum factorisation of one fetched row, the largest
     // coefficient of the row within the lane's element, and whether all of
     // them equal the ambient fixed point
     auto ytransform = [&](T c0, T c1, T f0, T f1, T(&v)[Q], T(&d)[Q], T(&f)[Q], T &mx, bool &am) {
+        c0 = okA ? c0 : T(0);
+        f0 = okA ? f0 : T(0);
+        c1 = okB ? c1 : T(0);
+        f1 = okB ? f1 : T(0);
         T cb[Q], fb[Q];
         cb[0] = c0;
         fb[0] = f0;
@@ -191,7 +198,7 @@ __device__ __forceinline__ void assemble_body(const AsmParams<T> &a, const int s
     T tv[Q][Q], td[Q][Q], tf[Q][Q], rmx[Q];
     bool ram[Q];
     T acc0[Q][Q], acc1[Q][Q], accf[Q][Q];
-    T pc0[Q], pc1[Q], pf0[Q], pf1[Q];
+    T pc0[Q] = {}, pc1[Q] = {}, pf0[Q] = {}, pf1[Q] = {};
     // live[s]: the dof row in slot s has received the contribution of an
     // evaluated element (wavefront-uniform); a row without one is exactly zero
     bool live[Q];
@@ -204,7 +211,7 @@ __device__ __forceinline__ void assemble_body(const AsmParams<T> &a, const int s
     // window rows E0 .. E0+P-1 in slots 0 .. P-1
 #pragma unroll
     for (int s = 0; s < P; ++s) {
-        T c0, c1, f0, f1;
+        T c0 = 0, c1 = 0, f0 = 0, f1 = 0;
         fetch(E0 + s, c0, c1, f0, f1);
         ytransform(c0, c1, f0, f1, tv[s], td[s], tf[s], rmx[s], ram[s]);
     }
