@@ -44,11 +44,12 @@ def parse():
     ap.add_argument("--tune", action="store_true",
                     help="with --kernels-only: autotune first (as the timed runs do)")
     ap.add_argument("--schedule", type=str, default=None,
-                    help="fixed exact line-solve schedule 'xlines,xwpl,ylines,ywpl,asmrows' "
+                    help="fixed exact line-solve schedule 'xlines,xwpl,ylines,ywpl,asmrows[,stacked]' "
                          "instead of autotuning")
     ap.add_argument("--window-schedule", type=str, default=None,
-                    help="fixed windowed line-solve schedule 'xlines,xrows,ylines,yrows,asmrows' "
-                         "(rows per lane) instead of autotuning")
+                    help="fixed windowed line-solve schedule 'xlines,xrows,ylines,yrows,asmrows[,stacked]' "
+                         "(rows per lane; stacked 0 or 1, else the plan's default tiling) "
+                         "instead of autotuning")
     ap.add_argument("--column-schedule", type=int, default=0,
                     help="with --kernels-only: column-wave x-line solves with this many rows "
                          "per chunk (16 or 32), after --window-schedule")
@@ -274,7 +275,8 @@ def copy_kernel(n_bytes, reps, torch):
 
 
 def apply_schedule(pl, spec, windowed=False):
-    xl, xw, yl, yw, ar = (int(v) for v in spec.split(","))
+    v = [int(x) for x in spec.split(",")]
+    xl, xw, yl, yw, ar = v[:5]
     if windowed:
         pl.set_window_schedule(0, xl, xw)
         pl.set_window_schedule(1, yl, yw)
@@ -282,6 +284,8 @@ def apply_schedule(pl, spec, windowed=False):
         pl.set_schedule(0, xl, xw)
         pl.set_schedule(1, yl, yw)
     pl.set_assembly_rows(ar)
+    if len(v) > 5:
+        pl.set_assembly_stacking(bool(v[5]))
 
 
 def ensemble_throughput(scs, steps, torch, iga):
