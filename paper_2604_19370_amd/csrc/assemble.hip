@@ -90,6 +90,14 @@ template <int N> struct Ic {
     static constexpr int value = N;
 };
 
+// read-only device data seen through the constant address space (loads the
+// compiler may issue as scalar loads where the address is uniform)
+template <typename T> using CT = const __attribute__((address_space(4))) T;
+template <typename T> __device__ __forceinline__ CT<T> *as_const(const T *p)
+{
+    return (CT<T> *)p;
+}
+
 // The work of one wavefront: dof rows [X0, X1) of strip `strip` (and the
 // elements of those rows).
 //   halo: also evaluate the p elements above the tile, so that its first p
@@ -127,25 +135,46 @@ __device__ __forceinline__ void assemble_body(const AsmParams<T> &a, const int s
         for (int qx = 0; qx < Q; ++qx) kxw[qx][qy] = k * a.wxq[qx];
     }
 
+    // Marching-loop form.  The hardware counts vector loads in issue order,
+    // so a step that waits for any load also waits for every row fetched
+    // before it.  PIPE (p <= 2) splits the march: a main loop over the steps
+    // whose row fetch lies inside the tile issues no other vector loads
+    // than those rows, each Q steps ahead of its use and with no branch
+    // around it, so that a step waits only for the row it consumes; it
+    // holds the element row's basis tables across steps (reloaded where
+    // they change, at the mesh ends) and reads the wind values by scalar
+    // loads.  The tile's last steps then run as before: a conditional fetch,
+    // tables loaded at every step.  Cubic kernels are at the register
+    // limit, where the held tables cost spills: they keep the one loop.
+    constexpr bool PIPE = P <= 2;
     // raw coefficients of row `row` for columns colA (and colB for the halo).
     // Every lane loads, from its column clamped into the mesh (lanes without
     // a halo column repeat their own); columns outside the mesh are zeroed
     // where the values are consumed, so no lane mask surrounds the loads.
     // Rows from min(X1, nel_x) + p on only feed elements that are not
-    // evaluated: they are not loaded, and the registers keep what they held.
+    // evaluated: they are not loaded (the registers keep what they held).
     const int rlim = min(X1, a.nel_x) + P;
     const unsigned offA = (unsigned)min(max(colA, 0), Ny - 1) * (unsigned)sizeof(T);
     const unsigned offB = okB ? (unsigned)colB * (unsigned)sizeof(T) : offA;
-    auto fetch = [&](int row, T &c0, T &c1, T &f0, T &f1) {
-        if (row < rlim) {
-            const size_t rb = (size_t)max(row, 0) * Ny * sizeof(T);
-            const char *sr = reinterpret_cast<const char *>(a.S) + rb;
-            const char *fr = reinterpret_cast<const char *>(a.F) + rb;
-            c0 = *reinterpret_cast<const T *>(sr + offA);
-            f0 = *reinterpret_cast<const T *>(fr + offA);
-            c1 = *reinterpret_cast<const T *>(sr + offB);
-            f1 = *reinterpret_cast<const T *>(fr + offB);
-        }
+    auto load_row = [&](int row, T &c0, T &c1, T &f0, T &f1) {
+        const size_t rb = (size_t)row * Ny * sizeof(T);
+        const char *sr = reinterpret_cast<const char *>(a.S) + rb;
+        const char *fr = reinterpret_cast<const char *>(a.F) + rb;
+        c0 = *reinterpret_cast<const T *>(sr + offA);
+        f0 = *reinterpret_cast<const T *>(fr + offA);
+        c1 = *reinterpret_cast<const T *>(sr + offB);
+        f1 = *reinterpret_cast<const T *>(fr + offB);
+    };
+    // mode Ic<0>: conditional.  Ic<1> (PIPE's main loop): the row lies below
+    // rlim, loaded without a branch.  Ic<2> (PIPE's window set-up): rows
+    // past rlim clamped to rlim - 1 (rows below 0 to 0; both only feed
+    // elements that are not evaluated) and loaded without a branch, so that
+    // the main loop starts with every load accounted for.
+    auto fetch = [&](int row, T &c0, T &c1, T &f0, T &f1, auto inrange) {
+        constexpr int mode = decltype(inrange)::value;
+        if constexpr (PIPE && mode == 1) load_row(max(row, 0), c0, c1, f0, f1);
+        else if constexpr (PIPE && mode == 2) load_row(min(max(row, 0), rlim - 1), c0, c1, f0, f1);
+        else if (row < rlim) load_row(max(row, 0), c0, c1, f0, f1);
     };
     // y half of the sum factorisation of one fetched row, the largest
     // coefficient of the row within the lane's element, and whether all of
@@ -212,21 +241,23 @@ __device__ __forceinline__ void assemble_body(const AsmParams<T> &a, const int s
 #pragma unroll
     for (int s = 0; s < P; ++s) {
         T c0 = 0, c1 = 0, f0 = 0, f1 = 0;
-        fetch(E0 + s, c0, c1, f0, f1);
+        fetch(E0 + s, c0, c1, f0, f1, Ic<2>{});
         ytransform(c0, c1, f0, f1, tv[s], td[s], tf[s], rmx[s], ram[s]);
     }
     // pending loads: step k consumes row E0 + P + k from slot k mod Q
 #pragma unroll
-    for (int s = 0; s < Q; ++s) fetch(E0 + P + s, pc0[s], pc1[s], pf0[s], pf1[s]);
+    for (int s = 0; s < Q; ++s) fetch(E0 + P + s, pc0[s], pc1[s], pf0[s], pf1[s], Ic<2>{});
 
     const T t_skip = a.t_skip;
-    auto step = [&](auto phase, int k) {
+    T bxv[Q][Q], bxd[Q][Q];   // basis tables of element row e2_held
+    int e2_held = -1;
+    auto step = [&](auto phase, int k, auto inrange) {
         constexpr int ph = decltype(phase)::value;
         constexpr int snew = (ph + P) % Q;   // slot of the new coefficient row / dof row ex+P
         const int ex = E0 + k;
         ytransform(pc0[ph], pc1[ph], pf0[ph], pf1[ph], tv[snew], td[snew], tf[snew], rmx[snew],
                    ram[snew]);
-        fetch(ex + P + Q, pc0[ph], pc1[ph], pf0[ph], pf1[ph]);
+        fetch(ex + P + Q, pc0[ph], pc1[ph], pf0[ph], pf1[ph], inrange);
         // an element whose coefficients all sit at the ambient fixed point
         // has no gradient, no net source and no ignition: in increment form
         // it contributes exactly nothing (the skip is wavefront-uniform)
@@ -236,18 +267,33 @@ __device__ __forceinline__ void assemble_body(const AsmParams<T> &a, const int s
         const bool quiet = !SRC && a.amb && __all(!eyok || eam);
         if (ex >= 0 && ex < a.nel_x && ex < X1 && !quiet) {
             const int e2 = (ex >= P && ex < a.nel_x - P) ? P : ex;   // interior tables coincide
-            const T *bxe = a.bx + (size_t)e2 * 2 * Q * Q;
-            T bxv[Q][Q], bxd[Q][Q], kyw[Q];
+            // the main loop of PIPE holds the tables (reloaded where they
+            // change); elsewhere they are loaded at every step
+            constexpr bool HOLD = PIPE && decltype(inrange)::value == 1;
+            if (!HOLD || e2 != e2_held) {
+                const T *bxe = a.bx + (size_t)e2 * 2 * Q * Q;
 #pragma unroll
-            for (int i = 0; i < Q; ++i)
+                for (int i = 0; i < Q; ++i)
 #pragma unroll
-                for (int q = 0; q < Q; ++q) {
-                    bxv[i][q] = bxe[i * Q + q];
-                    bxd[i][q] = bxe[Q * Q + i * Q + q];
-                }
+                    for (int q = 0; q < Q; ++q) {
+                        bxv[i][q] = bxe[i * Q + q];
+                        bxd[i][q] = bxe[Q * Q + i * Q + q];
+                    }
+                e2_held = HOLD ? e2 : -1;
+                // HOLD: wait here, on this rare path, for every vector load,
+                // so that after the branch the tables are known to have
+                // arrived on both paths and the common path waits only for
+                // the coefficient row it consumes
+                if constexpr (HOLD) __builtin_amdgcn_s_waitcnt(0x0f70);   // vmcnt(0)
+            }
+            T kyw[Q];
 #pragma unroll
-            for (int q = 0; q < Q; ++q)
-                kyw[q] = (-a.cy - a.bca * a.wx[(size_t)ex * Q + q]) * a.wxq[q];
+            for (int q = 0; q < Q; ++q) {
+                T w;
+                if constexpr (HOLD) w = as_const(a.wx)[(size_t)ex * Q + q];
+                else w = a.wx[(size_t)ex * Q + q];
+                kyw[q] = (-a.cy - a.bca * w) * a.wxq[q];
+            }
             T emx = rmx[0];
 #pragma unroll
             for (int s = 1; s < Q; ++s) emx = rmx[s] > emx ? rmx[s] : emx;
@@ -382,19 +428,39 @@ __device__ __forceinline__ void assemble_body(const AsmParams<T> &a, const int s
     };
 
     int k = 0;
-    for (; k + Q <= K; k += Q) {
-        step(Ic<0>{}, k);
-        step(Ic<1>{}, k + 1);
-        if constexpr (Q > 2) step(Ic<2>{}, k + 2);
-        if constexpr (Q > 3) step(Ic<3>{}, k + 3);
-    }
-    // fewer than Q steps remain
-    if (k < K) step(Ic<0>{}, k);
-    if constexpr (Q > 2) {
-        if (k + 1 < K) step(Ic<1>{}, k + 1);
-    }
-    if constexpr (Q > 3) {
-        if (k + 2 < K) step(Ic<2>{}, k + 2);
+    if constexpr (PIPE) {
+        // steps whose row fetch lies below rlim: branch-free loads; then the
+        // tile's last steps (about Q + p), whose fetches are conditional
+        const int Kf = min(K, rlim - E0 - P - Q);
+        for (; k + Q <= Kf; k += Q) {
+            step(Ic<0>{}, k, Ic<1>{});
+            step(Ic<1>{}, k + 1, Ic<1>{});
+            if constexpr (Q > 2) step(Ic<2>{}, k + 2, Ic<1>{});
+        }
+        for (; k + Q <= K; k += Q) {
+            step(Ic<0>{}, k, Ic<0>{});
+            step(Ic<1>{}, k + 1, Ic<0>{});
+            if constexpr (Q > 2) step(Ic<2>{}, k + 2, Ic<0>{});
+        }
+        if (k < K) step(Ic<0>{}, k, Ic<0>{});
+        if constexpr (Q > 2) {
+            if (k + 1 < K) step(Ic<1>{}, k + 1, Ic<0>{});
+        }
+    } else {
+        for (; k + Q <= K; k += Q) {
+            step(Ic<0>{}, k, Ic<0>{});
+            step(Ic<1>{}, k + 1, Ic<0>{});
+            if constexpr (Q > 2) step(Ic<2>{}, k + 2, Ic<0>{});
+            if constexpr (Q > 3) step(Ic<3>{}, k + 3, Ic<0>{});
+        }
+        // fewer than Q steps remain
+        if (k < K) step(Ic<0>{}, k, Ic<0>{});
+        if constexpr (Q > 2) {
+            if (k + 1 < K) step(Ic<1>{}, k + 1, Ic<0>{});
+        }
+        if constexpr (Q > 3) {
+            if (k + 2 < K) step(Ic<2>{}, k + 2, Ic<0>{});
+        }
     }
 }
 
