@@ -109,7 +109,8 @@ template <typename T> __device__ __forceinline__ CT<T> *as_const(const T *p)
 template <typename T, int P, bool FUEL, bool SRC = false>
 __device__ __forceinline__ void assemble_body(const AsmParams<T> &a, const int strip, const int X0,
                                               const int X1, const bool halo, const bool hold, const bool tail,
-                                              T *__restrict__ hd, T *__restrict__ tl)
+                                              T *__restrict__ hd, T *__restrict__ tl,
+                                              const T *__restrict__ ltab)
 {
     constexpr int Q = P + 1;
     const int lane = threadIdx.x & 63;
@@ -136,17 +137,20 @@ __device__ __forceinline__ void assemble_body(const AsmParams<T> &a, const int s
     }
 
     // Marching-loop form.  The hardware counts vector loads in issue order,
-    // so a step that waits for any load also waits for every row fetched
-    // before it.  PIPE (p <= 2) splits the march: a main loop over the steps
+    // so a step that waits for any vector load also waits for every row
+    // fetched before it.  The march is split: a main loop over the steps
     // whose row fetch lies inside the tile issues no other vector loads
     // than those rows, each Q steps ahead of its use and with no branch
-    // around it, so that a step waits only for the row it consumes; it
-    // holds the element row's basis tables across steps (reloaded where
-    // they change, at the mesh ends) and reads the wind values by scalar
-    // loads.  The tile's last steps then run as before: a conditional fetch,
-    // tables loaded at every step.  Cubic kernels are at the register
-    // limit, where the held tables cost spills: they keep the one loop.
-    constexpr bool PIPE = P <= 2;
+    // around it, so that a step waits only for the row it consumes.  There
+    // the element row's basis tables are held across steps and reloaded
+    // where they change, at the mesh ends (p <= 2), or read from LDS at
+    // every step (LTAB, p = 3, whose kernels are at the register limit),
+    // and the wind values come by scalar loads.  The tile's last steps use
+    // a conditional fetch and load the tables at every step.  FP64 cubic
+    // kernels spill more with the split loop and keep the single one (PIPE
+    // false: every step as the tile's last ones).
+    constexpr bool PIPE = !(sizeof(T) == 8 && P >= 3);
+    constexpr bool LTAB = PIPE && P >= 3;   // tables from ltab (LDS, one slot per distinct table)
     // raw coefficients of row `row` for columns colA (and colB for the halo).
     // Every lane loads, from its column clamped into the mesh (lanes without
     // a halo column repeat their own); columns outside the mesh are zeroed
@@ -165,8 +169,8 @@ __device__ __forceinline__ void assemble_body(const AsmParams<T> &a, const int s
         c1 = *reinterpret_cast<const T *>(sr + offB);
         f1 = *reinterpret_cast<const T *>(fr + offB);
     };
-    // mode Ic<0>: conditional.  Ic<1> (PIPE's main loop): the row lies below
-    // rlim, loaded without a branch.  Ic<2> (PIPE's window set-up): rows
+    // mode Ic<0>: conditional.  Ic<1> (the main loop): the row lies below
+    // rlim, loaded without a branch.  Ic<2> (the window set-up): rows
     // past rlim clamped to rlim - 1 (rows below 0 to 0; both only feed
     // elements that are not evaluated) and loaded without a branch, so that
     // the main loop starts with every load accounted for.
@@ -267,10 +271,22 @@ __device__ __forceinline__ void assemble_body(const AsmParams<T> &a, const int s
         const bool quiet = !SRC && a.amb && __all(!eyok || eam);
         if (ex >= 0 && ex < a.nel_x && ex < X1 && !quiet) {
             const int e2 = (ex >= P && ex < a.nel_x - P) ? P : ex;   // interior tables coincide
-            // the main loop of PIPE holds the tables (reloaded where they
-            // change); elsewhere they are loaded at every step
-            constexpr bool HOLD = PIPE && decltype(inrange)::value == 1;
-            if (!HOLD || e2 != e2_held) {
+            // the main loop holds the tables (reloaded where they change) or
+            // reads them from LDS; elsewhere they are loaded at every step
+            constexpr bool MAIN = PIPE && decltype(inrange)::value == 1;
+            constexpr bool HOLD = MAIN && !LTAB;
+            if constexpr (LTAB) {
+                // slots: the p head tables, the interior one, the p tail tables
+                const int slot = e2 <= P ? e2 : P + 1 + e2 - (a.nel_x - P);
+                const T *bxe = ltab + slot * 2 * Q * Q;
+#pragma unroll
+                for (int i = 0; i < Q; ++i)
+#pragma unroll
+                    for (int q = 0; q < Q; ++q) {
+                        bxv[i][q] = bxe[i * Q + q];
+                        bxd[i][q] = bxe[Q * Q + i * Q + q];
+                    }
+            } else if (!HOLD || e2 != e2_held) {
                 const T *bxe = a.bx + (size_t)e2 * 2 * Q * Q;
 #pragma unroll
                 for (int i = 0; i < Q; ++i)
@@ -290,7 +306,7 @@ __device__ __forceinline__ void assemble_body(const AsmParams<T> &a, const int s
 #pragma unroll
             for (int q = 0; q < Q; ++q) {
                 T w;
-                if constexpr (HOLD) w = as_const(a.wx)[(size_t)ex * Q + q];
+                if constexpr (MAIN) w = as_const(a.wx)[(size_t)ex * Q + q];
                 else w = a.wx[(size_t)ex * Q + q];
                 kyw[q] = (-a.cy - a.bca * w) * a.wxq[q];
             }
@@ -428,39 +444,28 @@ __device__ __forceinline__ void assemble_body(const AsmParams<T> &a, const int s
     };
 
     int k = 0;
-    if constexpr (PIPE) {
-        // steps whose row fetch lies below rlim: branch-free loads; then the
-        // tile's last steps (about Q + p), whose fetches are conditional
-        const int Kf = min(K, rlim - E0 - P - Q);
-        for (; k + Q <= Kf; k += Q) {
-            step(Ic<0>{}, k, Ic<1>{});
-            step(Ic<1>{}, k + 1, Ic<1>{});
-            if constexpr (Q > 2) step(Ic<2>{}, k + 2, Ic<1>{});
-        }
-        for (; k + Q <= K; k += Q) {
-            step(Ic<0>{}, k, Ic<0>{});
-            step(Ic<1>{}, k + 1, Ic<0>{});
-            if constexpr (Q > 2) step(Ic<2>{}, k + 2, Ic<0>{});
-        }
-        if (k < K) step(Ic<0>{}, k, Ic<0>{});
-        if constexpr (Q > 2) {
-            if (k + 1 < K) step(Ic<1>{}, k + 1, Ic<0>{});
-        }
-    } else {
-        for (; k + Q <= K; k += Q) {
-            step(Ic<0>{}, k, Ic<0>{});
-            step(Ic<1>{}, k + 1, Ic<0>{});
-            if constexpr (Q > 2) step(Ic<2>{}, k + 2, Ic<0>{});
-            if constexpr (Q > 3) step(Ic<3>{}, k + 3, Ic<0>{});
-        }
-        // fewer than Q steps remain
-        if (k < K) step(Ic<0>{}, k, Ic<0>{});
-        if constexpr (Q > 2) {
-            if (k + 1 < K) step(Ic<1>{}, k + 1, Ic<0>{});
-        }
-        if constexpr (Q > 3) {
-            if (k + 2 < K) step(Ic<2>{}, k + 2, Ic<0>{});
-        }
+    // steps whose row fetch lies below rlim: branch-free loads; then the
+    // tile's last steps (about Q + p), whose fetches are conditional
+    const int Kf = PIPE ? min(K, rlim - E0 - P - Q) : 0;
+    for (; k + Q <= Kf; k += Q) {
+        step(Ic<0>{}, k, Ic<1>{});
+        step(Ic<1>{}, k + 1, Ic<1>{});
+        if constexpr (Q > 2) step(Ic<2>{}, k + 2, Ic<1>{});
+        if constexpr (Q > 3) step(Ic<3>{}, k + 3, Ic<1>{});
+    }
+    for (; k + Q <= K; k += Q) {
+        step(Ic<0>{}, k, Ic<0>{});
+        step(Ic<1>{}, k + 1, Ic<0>{});
+        if constexpr (Q > 2) step(Ic<2>{}, k + 2, Ic<0>{});
+        if constexpr (Q > 3) step(Ic<3>{}, k + 3, Ic<0>{});
+    }
+    // fewer than Q steps remain
+    if (k < K) step(Ic<0>{}, k, Ic<0>{});
+    if constexpr (Q > 2) {
+        if (k + 1 < K) step(Ic<1>{}, k + 1, Ic<0>{});
+    }
+    if constexpr (Q > 3) {
+        if (k + 2 < K) step(Ic<2>{}, k + 2, Ic<0>{});
     }
 }
 
@@ -481,13 +486,27 @@ __device__ __forceinline__ void assemble_group(const AsmParams<T> &a, const int 
 {
     constexpr int G = 4;   // wavefronts per workgroup
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    // FP32 cubic kernels read the element rows' basis tables from LDS: the
+    // 2p + 1 distinct ones (p head, the interior, p tail), copied once per
+    // workgroup
+    constexpr bool LTAB = sizeof(T) == 4 && P >= 3;   // as in assemble_body
+    constexpr int TAB = 2 * (P + 1) * (P + 1);
+    __shared__ T ltab[LTAB ? (2 * P + 1) * TAB : 1];
+    if constexpr (LTAB) {
+        for (int i = threadIdx.x; i < (2 * P + 1) * TAB; i += blockDim.x) {
+            const int slot = i / TAB;
+            const int e = slot <= P ? slot : a.nel_x - P + (slot - P - 1);
+            ltab[i] = a.bx[(size_t)e * TAB + i % TAB];
+        }
+        __syncthreads();
+    }
     if constexpr (!STK) {
         // independent wavefronts: four neighbouring strips of one tile row
         const int gw = grp * G + w;
         if (gw >= a.nstrips * a.ntiles) return;
         const int X0 = (gw / a.nstrips) * a.rows;
         assemble_body<T, P, FUEL, SRC>(a, gw % a.nstrips, X0, min(X0 + a.rows, a.Nx), X0 > 0, false,
-                                       false, nullptr, nullptr);
+                                       false, nullptr, nullptr, ltab);
     } else {
         __shared__ T part[2][G][2 * P * 64];   // [head, tail][wavefront][(T, fuel) x row x lane]
         const int strip = grp % a.nstrips;
@@ -501,7 +520,8 @@ __device__ __forceinline__ void assemble_group(const AsmParams<T> &a, const int 
         const bool hold = holds(w);
         const bool halo = live && X0 > 0 && !hold;
         const bool tail = live && holds(w + 1);
-        if (live) assemble_body<T, P, FUEL, SRC>(a, strip, X0, X1, halo, hold, tail, part[0][w], part[1][w]);
+        if (live)
+            assemble_body<T, P, FUEL, SRC>(a, strip, X0, X1, halo, hold, tail, part[0][w], part[1][w], ltab);
         __syncthreads();
         if (hold) {
             const int lane = threadIdx.x & 63;
