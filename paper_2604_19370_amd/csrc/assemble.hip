@@ -23,8 +23,9 @@
 // fuel (loaded p+1 rows ahead, coalesced), contracts it in y with the lane's
 // own basis table (the y half of the sum factorisation, reused by the p+1
 // elements that share the row; neighbouring columns arrive by DPP rotates),
-// finishes the x half with the element row's basis table in scalar
-// registers, evaluates the pointwise terms at the (p+1)^2 points and
+// finishes the x half with the element row's basis table (one for the
+// whole wavefront: held in registers across steps, or read from LDS),
+// evaluates the pointwise terms at the (p+1)^2 points and
 // accumulates the x half of the test-function contraction into per-row
 // accumulators.  When a dof row is complete its y contraction is gathered from
 // the p neighbouring lanes and stored.  In the stacked variant a workgroup's
