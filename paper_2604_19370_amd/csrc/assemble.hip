@@ -130,12 +130,9 @@ __device__ __forceinline__ void assemble_body(const AsmParams<T> &a, const int s
             byv[b][q] = eyok ? a.by[(((size_t)ey * 2 + 0) * Q + b) * Q + q] : T(0);
             byd[b][q] = eyok ? a.by[(((size_t)ey * 2 + 1) * Q + b) * Q + q] : T(0);
         }
+    T wyl[Q];   // the lane's wind values, turned into kxw once the rows are requested
 #pragma unroll
-    for (int qy = 0; qy < Q; ++qy) {
-        const T k = -a.cx - a.bca * (eyok ? a.wy[(size_t)ey * Q + qy] : T(0));
-#pragma unroll
-        for (int qx = 0; qx < Q; ++qx) kxw[qx][qy] = k * a.wxq[qx];
-    }
+    for (int qy = 0; qy < Q; ++qy) wyl[qy] = eyok ? a.wy[(size_t)ey * Q + qy] : T(0);
 
     // Marching-loop form.  The hardware counts vector loads in issue order,
     // so a step that waits for any vector load also waits for every row
@@ -242,16 +239,26 @@ __device__ __forceinline__ void assemble_body(const AsmParams<T> &a, const int s
 #pragma unroll
         for (int q = 0; q < Q; ++q) acc0[i][q] = acc1[i][q] = accf[i][q] = T(0);
     }
-    // window rows E0 .. E0+P-1 in slots 0 .. P-1
+    // window rows E0 .. E0+P-1 (slots 0 .. P-1) and the pending rows (step
+    // k consumes row E0 + P + k from slot k mod Q), all requested before the
+    // window rows are transformed, so that their latencies overlap
+    T wc0[P], wc1[P], wf0[P], wf1[P];
 #pragma unroll
     for (int s = 0; s < P; ++s) {
-        T c0 = 0, c1 = 0, f0 = 0, f1 = 0;
-        fetch(E0 + s, c0, c1, f0, f1, Ic<2>{});
-        ytransform(c0, c1, f0, f1, tv[s], td[s], tf[s], rmx[s], ram[s]);
+        wc0[s] = wc1[s] = wf0[s] = wf1[s] = T(0);
+        fetch(E0 + s, wc0[s], wc1[s], wf0[s], wf1[s], Ic<2>{});
     }
-    // pending loads: step k consumes row E0 + P + k from slot k mod Q
 #pragma unroll
     for (int s = 0; s < Q; ++s) fetch(E0 + P + s, pc0[s], pc1[s], pf0[s], pf1[s], Ic<2>{});
+#pragma unroll
+    for (int s = 0; s < P; ++s)
+        ytransform(wc0[s], wc1[s], wf0[s], wf1[s], tv[s], td[s], tf[s], rmx[s], ram[s]);
+#pragma unroll
+    for (int qy = 0; qy < Q; ++qy) {
+        const T k = -a.cx - a.bca * wyl[qy];
+#pragma unroll
+        for (int qx = 0; qx < Q; ++qx) kxw[qx][qy] = k * a.wxq[qx];
+    }
 
     const T t_skip = a.t_skip;
     T bxv[Q][Q], bxd[Q][Q];   // basis tables of element row e2_held
