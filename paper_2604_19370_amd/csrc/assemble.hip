@@ -178,6 +178,17 @@ __device__ __forceinline__ void assemble_body(const AsmParams<T> &a, const int s
         else if constexpr (PIPE && mode == 2) load_row(min(max(row, 0), rlim - 1), c0, c1, f0, f1);
         else if (row < rlim) load_row(max(row, 0), c0, c1, f0, f1);
     };
+    // The fuel enters only the ignition and fuel terms, which FP32
+    // (increment-form) plans evaluate in the rare wavefronts near T_ig: there
+    // (LAZYF) the ring keeps the row's raw fuel coefficients and their y
+    // contraction is formed only where it is used, in the same order.
+    constexpr bool LAZYF = sizeof(T) == 4 && P <= 2;
+    auto ytrans_fuel = [&](const T(&fb)[Q], int q) {
+        T sf = 0;
+#pragma unroll
+        for (int b = 0; b < Q; ++b) sf += fb[b] * byv[b][q];
+        return sf;
+    };
     // y half of the sum factorisation of one fetched row, the largest
     // coefficient of the row within the lane's element, and whether all of
     // them equal the ambient fixed point
@@ -210,23 +221,28 @@ __device__ __forceinline__ void assemble_body(const AsmParams<T> &a, const int s
         }
 #pragma unroll
         for (int q = 0; q < Q; ++q) {
-            T sv = 0, sd = 0, sf = 0;
+            T sv = 0, sd = 0;
 #pragma unroll
             for (int b = 0; b < Q; ++b) {
                 sv += cb[b] * byv[b][q];
                 sd += cb[b] * byd[b][q];
-                sf += fb[b] * byv[b][q];
             }
             v[q] = sv;
             d[q] = sd;
-            f[q] = sf;
+        }
+        if constexpr (LAZYF) {
+#pragma unroll
+            for (int b = 0; b < Q; ++b) f[b] = fb[b];
+        } else {
+#pragma unroll
+            for (int q = 0; q < Q; ++q) f[q] = ytrans_fuel(fb, q);
         }
     };
 
     const int E0 = halo ? X0 - P : X0;       // first element row marched
     const int K = X1 - E0 + (tail ? P : 0);   // marching steps
     // rings indexed by (step + i) mod Q
-    T tv[Q][Q], td[Q][Q], tf[Q][Q], rmx[Q];
+    T tv[Q][Q], td[Q][Q], tf[Q][Q], rmx[Q];   // tf: raw fuel coefficients under LAZYF
     bool ram[Q];
     T acc0[Q][Q], acc1[Q][Q], accf[Q][Q];
     T pc0[Q] = {}, pc1[Q] = {}, pf0[Q] = {}, pf1[Q] = {};
@@ -364,17 +380,22 @@ __device__ __forceinline__ void assemble_body(const AsmParams<T> &a, const int s
                 }
             }
             if (hot) {
-                // ignition source and fuel terms (S and fuel re-evaluated)
+                // ignition source and fuel terms (S and fuel re-evaluated).
+                // Points by y, then x: each accumulator still receives its
+                // contributions in the order of qx.
 #pragma unroll
-                for (int qx = 0; qx < Q; ++qx) {
+                for (int qy = 0; qy < Q; ++qy) {
+                    T tfe[Q];   // the fuel rows' y contraction at qy, by ring slot
 #pragma unroll
-                    for (int qy = 0; qy < Q; ++qy) {
+                    for (int si = 0; si < Q; ++si) tfe[si] = LAZYF ? ytrans_fuel(tf[si], qy) : tf[si][qy];
+#pragma unroll
+                    for (int qx = 0; qx < Q; ++qx) {
                         T S = 0, F = 0;
 #pragma unroll
                         for (int i = 0; i < Q; ++i) {
                             const int si = (ph + i) % Q;
                             S += bxv[i][qx] * tv[si][qy];
-                            F += bxv[i][qx] * tf[si][qy];
+                            F += bxv[i][qx] * tfe[si];
                         }
                         T arr = T(0);
                         if (S > a.t_ig && F > a.fthr) arr = S * exp(-a.t_act / S);
